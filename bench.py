@@ -1,0 +1,183 @@
+"""Throughput benchmark of the RRS depth hot path on one MI355X.
+
+A step is one full RRS depth computation (every refinement of every query:
+directions, projection, univariate depth, argmin/pole update) over the
+workload's queries, with X and Z already resident in HBM (device pointers).
+The default workload is projection depth on 10000 x 20 Gaussian data
+(Wishart covariance), 1000 queries (800 in-law, 200 Cauchy), K = 5000,
+r = 20, alpha = 0.5.
+
+Prints ONE JSON line:
+  value     query x direction x point projections per second (whole job)
+  roofline  the dominant kernel's achieved rate against its bound, from its
+            average launch duration measured with HIP events on its launch
+            stream during the timed steps
+  cpu_baseline  the FP64 oracle on a bounded query sample on the host cores
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
+FP64_VALU_PEAK_TFLOPS = 78.6   # 256 CU x 4 SIMD x 16 lanes x 2 flop x 2.4 GHz
+
+WORKLOADS = {
+    "c2": ("c2", "projection"),
+    "c1": ("c1", "halfspace"),
+    "c1b": ("c1b", "halfspace"),
+    "c3": ("c3", "apd"),
+    "c5h": ("c5", "halfspace"),
+    "c5p": ("c5", "projection"),
+}
+
+
+def kernel_model(name: str, notion: str, d: int):
+    """Algorithmic cost per work unit of each kernel."""
+    if name == "k_proj_f64":
+        if notion == "halfspace":
+            return {"bound": "alu", "per_unit": 2.0 * d, "unit": "TFLOP/s",
+                    "peak": FP64_VALU_PEAK_TFLOPS, "scale": 1e-12,
+                    "what": f"2d = {2 * d} FP64 flops per projection"}
+        return {"bound": "hbm", "per_unit": 8.0, "unit": "GB/s", "peak": HBM_PEAK_GBS,
+                "scale": 1e-9, "what": "8 B written per projection (binary64 column)"}
+    if name == "k_select":
+        return {"bound": "hbm", "per_unit": 8.0, "unit": "GB/s", "peak": HBM_PEAK_GBS,
+                "scale": 1e-9, "what": "8 B read per projection (binary64 column)"}
+    return None
+
+
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(w, notion, max_queries):
+    import numpy as np
+
+    import oracle
+    oracle.build(force=False)
+    threads = oracle.max_threads()
+    nq = max(1, min(threads, max_queries, w.nq))
+    qs = np.arange(nq)
+    t0 = time.perf_counter()
+    oracle.rrs_depth_idx(notion, w.X, w.Z[qs], qs, w.K, w.n_refine, w.cap_shrink, w.rrs_seed,
+                         nthreads=nq)
+    dt = time.perf_counter() - t0
+    proj = nq * w.n_refine * w.m_dirs * w.n
+    return {"value": proj / dt, "unit": "projections/s", "cores": int(nq), "kind": "oracle",
+            "sample": f"queries 0..{nq - 1} of {w.nq} (all {w.n_refine} refinements, "
+                      f"{w.n_refine * w.m_dirs} directions each), one OpenMP thread per "
+                      f"query, {dt:.1f} s wall on {cpu_model()}",
+            "seconds": dt}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="c2", choices=sorted(WORKLOADS))
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-queries", type=int, default=32)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (queries shard "
+              f"across GPUs without communication, see DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_2506_08262_amd import rrs, workloads
+    wname, notion = WORKLOADS[args.workload]
+    w = workloads.make(wname, **({"notion": notion} if wname == "c5" else {}))
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    X = torch.from_numpy(w.X).to(dev)
+    Z = torch.from_numpy(w.Z).to(dev)
+    fn = rrs.DEPTH_FUNCS[notion]
+    print(f"[bench] workload {args.workload} ({notion}) n={w.n} d={w.d} queries={w.nq} "
+          f"K={w.K} r={w.n_refine} alpha={w.cap_shrink}", file=sys.stderr, flush=True)
+
+    for i in range(args.warmup):
+        fn(X, Z, w.K, w.n_refine, w.cap_shrink, w.rrs_seed)
+        torch.cuda.synchronize()
+        print(f"[bench] warmup {i + 1}/{args.warmup} done", file=sys.stderr, flush=True)
+
+    rrs.rrs_profile_enable(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        out = fn(X, Z, w.K, w.n_refine, w.cap_shrink, w.rrs_seed)
+        print(f"[bench] step {i + 1}/{args.steps}", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prof = rrs.rrs_profile_read()
+    rrs.rrs_profile_enable(False)
+    depth = out["depth"].cpu().numpy()
+
+    sec = (t1 - t0) / args.steps
+    proj = w.projections
+    value = proj / sec
+
+    # dominant kernel's roofline from its live HIP-event timings
+    roof = None
+    dom = max(prof.items(), key=lambda kv: kv[1]["total_ms"]) if prof else None
+    if dom is not None:
+        name, st = dom
+        model = kernel_model(name, notion, w.d)
+        if model is not None:
+            units_per_launch = st["work_units"] / st["launches"]
+            achieved = model["per_unit"] * units_per_launch / (st["avg_ms"] * 1e-3) * model["scale"]
+            roof = {"kernel": name, "bound": model["bound"], "achieved": achieved,
+                    "peak": model["peak"], "unit": model["unit"], "frac": achieved / model["peak"],
+                    "traffic": None, "avg_launch_ms": st["avg_ms"],
+                    "units_per_launch": units_per_launch, "per_unit": model["what"]}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        print("[bench] cpu baseline (oracle) ...", file=sys.stderr, flush=True)
+        cpu = cpu_baseline(w, notion, args.cpu_queries)
+
+    line = {
+        "metric": "query·direction·point projections/s",
+        "value": value,
+        "unit": "projections/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": sec * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"{args.workload}: {notion} depth, {w.recipe}; K={w.K}, "
+                               f"n_refine={w.n_refine}, cap_shrink={w.cap_shrink}",
+                   "notion": notion, "n": w.n, "d": w.d, "queries": w.nq, "K": w.K,
+                   "n_refine": w.n_refine, "cap_shrink": w.cap_shrink, "precision": "f64",
+                   "projections_per_step": proj},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+        "kernels": {k: {"avg_ms": v["avg_ms"], "launches_per_step": v["launches"] / args.steps,
+                        "ms_per_step": v["total_ms"] / args.steps} for k, v in prof.items()},
+        "depth_mean": float(depth.mean()),
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,156 @@
+/*
+ * rrs.h -- C ABI of librrs: Refined Random Search (RRS) projection-based
+ * depths on AMD Instinct MI355X (gfx950).
+ *
+ * Method: Leone, Mozharovskyi, Bounie, "Massive parallelization of
+ * projection-based depths" (arXiv 2506.08262).  For every query z_q (a row of
+ * Z) the library approximates
+ *
+ *     D(z_q | X) = inf over unit u of D(z_q.u | X u)          (Definition 2)
+ *
+ * by RRS (Alg. 1; parallel form Alg. 4 / Alg. S5): r = n_refine refinements
+ * of m_dir = ceil(K / r) random directions each -- uniform on the sphere in
+ * the first refinement (Alg. S1), then uniform in angle inside a spherical cap
+ * of half-angle (pi/2) * cap_shrink^(l-1) around the query's current best
+ * direction (Alg. S4) -- keeping the smallest univariate depth found
+ * (Corollary 1: every value returned is an upper bound of the exact depth).
+ * The univariate depths are those of Sec. 2 (halfspace, projection,
+ * asymmetric projection).  Directions come from a counter-based Philox4x64-10
+ * stream keyed by (seed, query index), so a query's result does not depend on
+ * which other queries share the call.
+ *
+ * Conventions shared by all entry points
+ * --------------------------------------
+ *  X      : n x d data, row-major binary64 (row i = point x_i).
+ *  Z      : m x d queries, row-major binary64.  (m is the number of queries;
+ *           the number of directions per refinement is ceil(K / n_refine).)
+ *  K      : total directions per query, >= 1; r * ceil(K/r) are evaluated.
+ *  n_refine: number of refinements r, >= 1.
+ *  cap_shrink: alpha in (0, 1], the cap half-angle factor per refinement.
+ *  seed   : Philox key word 0.
+ *  depth  : m outputs, binary64, written only when the call returns RRS_OK.
+ *  opts   : may be NULL (host pointers, default stream, no optional outputs).
+ *
+ * Memory: with opts->device_ptrs == 0 every array is host memory and the call
+ * returns after the result is in place.  With device_ptrs != 0 every array
+ * (X, Z, outputs, optional outputs) is device memory on the current HIP
+ * device; work is issued on opts->stream and the call still synchronises that
+ * stream before returning.  The caller owns all arrays; the library keeps no
+ * pointer after return.  The library owns a per-device workspace that grows
+ * on demand and is released by rrs_release_workspace().
+ *
+ * Errors: every entry point returns a status and never aborts; the text of
+ * the last failure on the calling thread is available from rrs_last_error().
+ * RRS_E_INVAL: a NULL pointer with a positive size, n < 1, d < 2, K < 1,
+ * n_refine < 1, cap_shrink outside (0, 1], a non-finite value in X or Z (host
+ * pointers only), or an unknown precision.  m == 0 is a no-op returning RRS_OK.
+ * RRS_E_NOMEM: device memory could not be obtained.  RRS_E_DEVICE: a HIP
+ * error (text in rrs_last_error).  Calls from several threads are serialised.
+ */
+#ifndef RRS_H
+#define RRS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    RRS_OK = 0,
+    RRS_E_INVAL = 1,
+    RRS_E_NOMEM = 2,
+    RRS_E_DEVICE = 3,
+    RRS_E_INTERNAL = 6
+} rrs_status;
+
+/* Arithmetic of the projection step.  RRS_F64: every projection is the
+ * binary64 fused multiply-add chain over coordinates 0..d-1 of the shared
+ * recipe, so counts, order statistics and depths are exact (bit-identical to
+ * the FP64 oracle). */
+typedef enum {
+    RRS_F64 = 0
+} rrs_precision;
+
+typedef struct {
+    int32_t precision;        /* rrs_precision; default RRS_F64 */
+    int32_t device_ptrs;      /* 0: host arrays; 1: device arrays */
+    void *stream;             /* hipStream_t for device_ptrs == 1 (NULL: default) */
+    int64_t query_offset;     /* stream index of Z's first row (default 0) */
+    double *poles;            /* optional out [m x d]: final pole per query */
+    int64_t *trace;           /* optional out [m x n_refine x 3]: per refinement
+                                 j*, improved (0/1), minimum (int64 count for
+                                 halfspace, binary64 bits otherwise) */
+    size_t workspace_limit;   /* bytes the per-refinement scratch may use;
+                                 0: library default */
+} rrs_opts;
+
+/* Halfspace (Tukey) depth, Sec. 2: min(#{x_i.u <= z.u}, #{x_i.u >= z.u}) / n,
+ * minimised over the RRS directions.  count (may be NULL) receives the
+ * integer minimum count per query; depth = count / n. */
+rrs_status rrs_depth_halfspace(const double *X, int64_t n, int64_t d,
+                               const double *Z, int64_t m, int64_t K,
+                               int32_t n_refine, double cap_shrink, uint64_t seed,
+                               double *depth, int64_t *count, const rrs_opts *opts);
+
+/* Projection depth, Sec. 2: (1 + |z.u - med(Xu)| / MAD(Xu))^-1 minimised over
+ * the RRS directions; MAD = med |x_i.u - med(Xu)|.  MAD == 0 gives 1 when
+ * z.u == med(Xu), else 0. */
+rrs_status rrs_depth_projection(const double *X, int64_t n, int64_t d,
+                                const double *Z, int64_t m, int64_t K,
+                                int32_t n_refine, double cap_shrink, uint64_t seed,
+                                double *depth, const rrs_opts *opts);
+
+/* Asymmetric projection depth, Sec. 2: (1 + (z.u - med(Xu))_+ / MAD_+(Xu))^-1
+ * minimised over the RRS directions; MAD_+ is the median of the strictly
+ * positive deviations x_i.u - med(Xu).  No positive deviation gives 1 when
+ * z.u <= med(Xu), else 0. */
+rrs_status rrs_depth_apd(const double *X, int64_t n, int64_t d,
+                         const double *Z, int64_t m, int64_t K,
+                         int32_t n_refine, double cap_shrink, uint64_t seed,
+                         double *depth, const rrs_opts *opts);
+
+/* Text of the last non-OK status returned on this thread ("" if none). */
+const char *rrs_last_error(void);
+
+/* Frees the workspace of every device.  Safe to call at any time between
+ * calls. */
+rrs_status rrs_release_workspace(void);
+
+/* Library version as major*10000 + minor*100 + patch. */
+int32_t rrs_version(void);
+
+/* Per-kernel timing.  While enabled, every kernel launch of the depth calls
+ * is bracketed by HIP events on the launch stream; each call reads them back
+ * after synchronising its stream.  rrs_profile_enable(1) turns timing on and
+ * clears the totals, rrs_profile_enable(0) turns it off.  rrs_profile_read
+ * copies up to max_entries totals (one per kernel that ran) into out and
+ * returns how many it wrote (out may be NULL to count them).  work_units is
+ * the sum over launches of the units each launch processed: projections
+ * (query x direction x point) for k_proj_f64 and k_select, coordinates for
+ * k_gen_dirs, directions for k_argmin_pole. */
+typedef struct {
+    char name[32];
+    int64_t launches;
+    double total_ms;
+    double work_units;
+} rrs_kernel_stat;
+
+rrs_status rrs_profile_enable(int32_t on);
+int32_t rrs_profile_read(rrs_kernel_stat *out, int32_t max_entries);
+
+/* Diagnostic for parity checks of the direction generator (step a1 alone):
+ * writes the m_dir directions of refinement l (1-based) for the query whose
+ * stream index is q, generated on the device exactly as inside the depth
+ * calls, with cap scale phi = cap_shrink^(l-1) and pole p (both ignored for
+ * l == 1).  pole: host [d]; out: host [m_dir x d], row-major.  Returns
+ * RRS_E_INVAL for d < 2, m_dir < 1, l < 1 or NULL pointers. */
+rrs_status rrs_debug_directions(int64_t d, int64_t m_dir, int32_t l, double phi, uint64_t seed,
+                                uint64_t q, const double *pole, double *out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RRS_H */

@@ -66,6 +66,8 @@ def lib():
                                   p, p, p, p]
         L.o_rrs_depth.argtypes = [ctypes.c_int, p, i64, i64, p, i64, u64, i64, i32, dbl,
                                   u64, p, p, p, i32]
+        L.o_rrs_depth_idx.argtypes = [ctypes.c_int, p, i64, i64, p, i64, p, i64, i32, dbl,
+                                      u64, p, p, p, i32]
         L.o_max_threads.restype = i32
         _lib = L
     return _lib
@@ -189,6 +191,29 @@ def rrs_depth(notion: str, X, Z, K: int, n_refine: int, cap_shrink: float, seed:
     lib().o_rrs_depth(NOTIONS[notion], _ptr(X), n, d, _ptr(Z), nq, int(q0), int(K),
                       int(n_refine), float(cap_shrink), int(seed), _ptr(depth), _ptr(count),
                       _ptr(poles) if with_poles else None, int(nthreads))
+    out = {"depth": depth}
+    if notion == "halfspace":
+        out["count"] = count
+    if with_poles:
+        out["poles"] = poles
+    return out
+
+
+def rrs_depth_idx(notion: str, X, Z, qidx, K: int, n_refine: int, cap_shrink: float,
+                  seed: int, nthreads: int = 0, with_poles: bool = False):
+    """Depth of every row of Z, row i keyed by stream index qidx[i]."""
+    X = _f64(X)
+    Z = _f64(Z)
+    n, d = X.shape
+    nq = Z.shape[0]
+    q = np.ascontiguousarray(qidx, dtype=np.uint64)
+    assert q.shape == (nq,) and Z.shape[1] == d
+    depth = np.zeros(nq, dtype=np.float64)
+    count = np.zeros(nq, dtype=np.int64)
+    poles = np.zeros((nq, d), dtype=np.float64) if with_poles else None
+    lib().o_rrs_depth_idx(NOTIONS[notion], _ptr(X), n, d, _ptr(Z), nq, _ptr(q), int(K),
+                          int(n_refine), float(cap_shrink), int(seed), _ptr(depth), _ptr(count),
+                          _ptr(poles) if with_poles else None, int(nthreads))
     out = {"depth": depth}
     if notion == "halfspace":
         out["count"] = count

@@ -431,3 +431,22 @@ int32_t o_max_threads(void)
     return 1;
 #endif
 }
+
+/* Queries with explicit stream indices qidx[i] (row i of Z), in parallel. */
+void o_rrs_depth_idx(int notion, const double *X, int64_t n, int64_t d,
+                     const double *Z, int64_t nq, const uint64_t *qidx, int64_t K,
+                     int32_t r, double alpha, uint64_t seed, double *depth,
+                     int64_t *count, double *poles, int32_t nthreads)
+{
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#else
+    (void)nthreads;
+#endif
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t i = 0; i < nq; ++i) {
+        o_rrs_query(notion, X, n, d, Z + i * d, qidx[i], K, r, alpha, seed,
+                    &depth[i], count ? &count[i] : NULL,
+                    poles ? poles + i * d : NULL, NULL);
+    }
+}

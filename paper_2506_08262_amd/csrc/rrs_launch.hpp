@@ -1,0 +1,64 @@
+// rrs_launch.hpp -- host-side launchers of the RRS kernels (internal).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace rrs {
+
+enum { NOTION_HALFSPACE = 0, NOTION_PROJECTION = 1, NOTION_APD = 2 };
+
+constexpr int kProjJT = 16;  // directions per projection workgroup
+
+struct GenArgs {
+    int64_t d, m, ldm, qb;
+    int32_t l;
+    double phi;
+    uint64_t seed, qbase;
+    const double *pole;
+    double *UT;
+};
+
+struct ProjArgs {
+    const double *XT;
+    int64_t ldx, n, d;
+    const double *Z;
+    const double *UT;
+    int64_t ldm, m, qb;
+    uint32_t *cnt;
+    double *T;
+};
+
+struct SelectArgs {
+    const double *T;
+    int64_t n, m, ldm, qb;
+    double *Dj;
+};
+
+struct ArgminArgs {
+    int64_t m, ldm, d, qb;
+    const uint32_t *cnt;
+    const double *Dj;
+    const double *UT;
+    double *pole;
+    double *best_d;
+    int64_t *best_c;
+    int64_t *trace;
+    int32_t l, r;
+};
+
+hipError_t launch_gen_dirs(const GenArgs &a, hipStream_t st);
+hipError_t launch_transpose(const double *X, int64_t n, int64_t d, int64_t ldx, double *XT,
+                            hipStream_t st);
+hipError_t launch_fill_u32(uint32_t *p, int64_t count, uint32_t v, hipStream_t st);
+hipError_t launch_proj_f64(const ProjArgs &a, bool count_mode, hipStream_t st);
+int64_t select_lds_max_n(int device);
+hipError_t launch_select(const SelectArgs &a, int notion, bool lds, hipStream_t st);
+hipError_t launch_argmin(const ArgminArgs &a, bool half, hipStream_t st);
+hipError_t launch_init_state(int64_t qb, int64_t d, int64_t n, double *pole, double *best_d,
+                             int64_t *best_c, hipStream_t st);
+hipError_t launch_finalize(int64_t qb, int64_t d, int64_t n, bool half, const double *pole,
+                           const double *best_d, const int64_t *best_c, double *depth,
+                           int64_t *count, double *poles_out, hipStream_t st);
+
+}  // namespace rrs

@@ -1,0 +1,236 @@
+"""Python binding of librrs (the C ABI in include/rrs.h).
+
+Argument marshalling only: numpy arrays are passed as host pointers, torch
+tensors on a ROCm device as device pointers together with torch's current HIP
+stream.  Every step of the depth computation runs in the library's HIP
+kernels; there is no fallback path -- if the library is missing or fails to
+load, every call raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "librrs.so")
+
+RRS_OK, RRS_E_INVAL, RRS_E_NOMEM, RRS_E_DEVICE, RRS_E_INTERNAL = 0, 1, 2, 3, 6
+RRS_F64 = 0
+PRECISIONS = {"f64": RRS_F64}
+STATUS_NAMES = {0: "RRS_OK", 1: "RRS_E_INVAL", 2: "RRS_E_NOMEM", 3: "RRS_E_DEVICE",
+                6: "RRS_E_INTERNAL"}
+
+EXPORTED = ["rrs_depth_halfspace", "rrs_depth_projection", "rrs_depth_apd",
+            "rrs_last_error", "rrs_release_workspace", "rrs_version", "rrs_debug_directions",
+            "rrs_profile_enable", "rrs_profile_read"]
+
+
+class RRSError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+class rrs_opts(ctypes.Structure):
+    _fields_ = [("precision", ctypes.c_int32),
+                ("device_ptrs", ctypes.c_int32),
+                ("stream", ctypes.c_void_p),
+                ("query_offset", ctypes.c_int64),
+                ("poles", ctypes.c_void_p),
+                ("trace", ctypes.c_void_p),
+                ("workspace_limit", ctypes.c_size_t)]
+
+
+class rrs_kernel_stat(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char * 32),
+                ("launches", ctypes.c_int64),
+                ("total_ms", ctypes.c_double),
+                ("work_units", ctypes.c_double)]
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load librrs.so (raises if it is not built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"librrs.so not built at {path}; run __graft_entry__.build()")
+    L = ctypes.CDLL(path)
+    p, i64, i32, u64, dbl = (ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_uint64,
+                             ctypes.c_double)
+    common = [p, i64, i64, p, i64, i64, i32, dbl, u64, p]
+    L.rrs_depth_halfspace.argtypes = common + [p, ctypes.POINTER(rrs_opts)]
+    L.rrs_depth_halfspace.restype = ctypes.c_int
+    L.rrs_depth_projection.argtypes = common + [ctypes.POINTER(rrs_opts)]
+    L.rrs_depth_projection.restype = ctypes.c_int
+    L.rrs_depth_apd.argtypes = common + [ctypes.POINTER(rrs_opts)]
+    L.rrs_depth_apd.restype = ctypes.c_int
+    L.rrs_last_error.restype = ctypes.c_char_p
+    L.rrs_release_workspace.restype = ctypes.c_int
+    L.rrs_version.restype = ctypes.c_int32
+    L.rrs_debug_directions.argtypes = [i64, i64, i32, dbl, u64, u64, p, p]
+    L.rrs_debug_directions.restype = ctypes.c_int
+    L.rrs_profile_enable.argtypes = [i32]
+    L.rrs_profile_enable.restype = ctypes.c_int
+    L.rrs_profile_read.argtypes = [ctypes.POINTER(rrs_kernel_stat), i32]
+    L.rrs_profile_read.restype = i32
+    _lib = L
+    return L
+
+
+def _check(status: int):
+    if status != RRS_OK:
+        raise RRSError(status, load().rrs_last_error().decode())
+
+
+def _is_torch(a) -> bool:
+    return type(a).__module__.startswith("torch")
+
+
+def _prep(a, name, dtype):
+    """Returns (pointer, keepalive, on_device)."""
+    if _is_torch(a):
+        import torch
+        if a.dtype != dtype[1]:
+            raise TypeError(f"{name} must be {dtype[1]}")
+        if not a.is_contiguous():
+            raise ValueError(f"{name} must be contiguous")
+        return ctypes.c_void_p(a.data_ptr()), a, a.is_cuda
+    arr = np.ascontiguousarray(a, dtype=dtype[0])
+    return arr.ctypes.data_as(ctypes.c_void_p), arr, False
+
+
+def _alloc_like(X, shape, np_dtype, torch_dtype):
+    if _is_torch(X):
+        import torch
+        return torch.empty(shape, dtype=torch_dtype, device=X.device)
+    return np.empty(shape, dtype=np_dtype)
+
+
+def _run(fn_name, X, Z, K, n_refine, cap_shrink, seed, precision, query_offset,
+         want_count, want_poles, want_trace, stream, workspace_limit):
+    import_torch = _is_torch(X) or _is_torch(Z)
+    f64 = (np.float64, None)
+    i64 = (np.int64, None)
+    if import_torch:
+        import torch
+        f64 = (np.float64, torch.float64)
+        i64 = (np.int64, torch.int64)
+    Xp, Xk, Xdev = _prep(X, "X", f64)
+    Zp, Zk, Zdev = _prep(Z, "Z", f64)
+    if Xdev != Zdev:
+        raise ValueError("X and Z must both be host or both be device arrays")
+    n, d = int(Xk.shape[0]), int(Xk.shape[1])
+    nq = int(Zk.shape[0])
+    if Zk.shape[1] != d:
+        raise ValueError("Z must have d columns")
+    tdt = None
+    if import_torch:
+        import torch
+        tdt = (torch.float64, torch.int64)
+    depth = _alloc_like(Xk, (nq,), np.float64, tdt[0] if tdt else None)
+    count = _alloc_like(Xk, (nq,), np.int64, tdt[1] if tdt else None) if want_count else None
+    poles = _alloc_like(Xk, (nq, d), np.float64, tdt[0] if tdt else None) if want_poles else None
+    trace = (_alloc_like(Xk, (nq, n_refine, 3), np.int64, tdt[1] if tdt else None)
+             if want_trace else None)
+
+    def ptr(a):
+        if a is None:
+            return None
+        return ctypes.c_void_p(a.data_ptr()) if _is_torch(a) else a.ctypes.data_as(ctypes.c_void_p)
+
+    o = rrs_opts()
+    o.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+    o.device_ptrs = 1 if Xdev else 0
+    if Xdev:
+        import torch
+        s = stream if stream is not None else torch.cuda.current_stream(Xk.device)
+        o.stream = ctypes.c_void_p(s.cuda_stream if hasattr(s, "cuda_stream") else int(s))
+    o.query_offset = int(query_offset)
+    o.poles = ptr(poles)
+    o.trace = ptr(trace)
+    o.workspace_limit = int(workspace_limit or 0)
+    L = load()
+    args = [Xp, n, d, Zp, nq, int(K), int(n_refine), float(cap_shrink), int(seed), ptr(depth)]
+    if fn_name == "rrs_depth_halfspace":
+        args.append(ptr(count))
+    args.append(ctypes.byref(o))
+    _check(getattr(L, fn_name)(*args))
+    out = {"depth": depth}
+    if want_count:
+        out["count"] = count
+    if want_poles:
+        out["poles"] = poles
+    if want_trace:
+        out["trace"] = trace
+    return out
+
+
+def rrs_depth_halfspace(X, Z, K, n_refine, cap_shrink, seed=0, precision="f64", query_offset=0,
+                        want_poles=False, want_trace=False, stream=None, workspace_limit=0):
+    """Halfspace depth of each row of Z; returns dict(depth, count[, poles, trace])."""
+    return _run("rrs_depth_halfspace", X, Z, K, n_refine, cap_shrink, seed, precision,
+                query_offset, True, want_poles, want_trace, stream, workspace_limit)
+
+
+def rrs_depth_projection(X, Z, K, n_refine, cap_shrink, seed=0, precision="f64", query_offset=0,
+                         want_poles=False, want_trace=False, stream=None, workspace_limit=0):
+    """Projection depth of each row of Z; returns dict(depth[, poles, trace])."""
+    return _run("rrs_depth_projection", X, Z, K, n_refine, cap_shrink, seed, precision,
+                query_offset, False, want_poles, want_trace, stream, workspace_limit)
+
+
+def rrs_depth_apd(X, Z, K, n_refine, cap_shrink, seed=0, precision="f64", query_offset=0,
+                  want_poles=False, want_trace=False, stream=None, workspace_limit=0):
+    """Asymmetric projection depth of each row of Z; returns dict(depth[, poles, trace])."""
+    return _run("rrs_depth_apd", X, Z, K, n_refine, cap_shrink, seed, precision, query_offset,
+                False, want_poles, want_trace, stream, workspace_limit)
+
+
+DEPTH_FUNCS = {"halfspace": rrs_depth_halfspace, "projection": rrs_depth_projection,
+               "apd": rrs_depth_apd}
+
+
+def depth(notion, X, Z, K, n_refine, cap_shrink, seed=0, **kw):
+    return DEPTH_FUNCS[notion](X, Z, K, n_refine, cap_shrink, seed, **kw)
+
+
+def rrs_debug_directions(d, m_dir, l, phi, seed, q, pole) -> np.ndarray:
+    """Directions of refinement l for stream query index q, from the device."""
+    pole = np.ascontiguousarray(pole, dtype=np.float64)
+    out = np.zeros((m_dir, d), dtype=np.float64)
+    _check(load().rrs_debug_directions(int(d), int(m_dir), int(l), float(phi), int(seed), int(q),
+                                       pole.ctypes.data_as(ctypes.c_void_p),
+                                       out.ctypes.data_as(ctypes.c_void_p)))
+    return out
+
+
+def rrs_release_workspace():
+    _check(load().rrs_release_workspace())
+
+
+def rrs_version() -> int:
+    return int(load().rrs_version())
+
+
+def rrs_profile_enable(on: bool = True):
+    _check(load().rrs_profile_enable(1 if on else 0))
+
+
+def rrs_profile_read() -> dict:
+    """{kernel name: {launches, total_ms, avg_ms, work_units}} of the timed launches."""
+    L = load()
+    arr = (rrs_kernel_stat * 16)()
+    k = L.rrs_profile_read(arr, 16)
+    out = {}
+    for i in range(k):
+        e = arr[i]
+        out[e.name.decode()] = {"launches": int(e.launches), "total_ms": float(e.total_ms),
+                                "avg_ms": float(e.total_ms) / max(int(e.launches), 1),
+                                "work_units": float(e.work_units)}
+    return out
