@@ -292,11 +292,6 @@ __device__ uint64_t select_kth(const double *g, const double *s, int64_t n, doub
     uint64_t prefix = 0, pmask = 0;
     for (int shift = 56; shift >= 0; shift -= 8) {
         for (int b = tid; b < 256; b += kSelThreads) sh.hist[b] = 0;
-        if (tid == 0) {
-            sh.sel_bucket = 0;
-            sh.sel_before = 0;
-            sh.sel_count = 0;
-        }
         block_sync();
         for (int64_t i0 = 0; i0 < n; i0 += kSelThreads) {
             const int64_t i = i0 + tid;

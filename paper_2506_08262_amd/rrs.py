@@ -60,6 +60,15 @@ def load(path: str = LIB_PATH):
         return _lib
     if not os.path.exists(path):
         raise RuntimeError(f"librrs.so not built at {path}; run __graft_entry__.build()")
+    # One HIP runtime per process: torch ships its own libamdhip64 (same
+    # soname as the system one librrs links against).  Loading torch first
+    # makes librrs bind to torch's copy, so device pointers and streams from
+    # torch are valid in the library; loading librrs first would make torch
+    # load a second runtime that cannot see the GPU.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     L = ctypes.CDLL(path)
     p, i64, i32, u64, dbl = (ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_uint64,
                              ctypes.c_double)

@@ -176,3 +176,14 @@ def test_c2_projection_full_size_sampled():
     assert np.all((D > 0) & (D <= 1))
     # Cauchy queries (last 200) are far less central than in-law ones
     assert np.median(D[800:]) < np.median(D[:800])
+
+
+def test_single_hip_runtime_in_process():
+    import torch
+    torch.zeros(1, device="cuda:0")
+    rrs.load()
+    libs = set()
+    for line in open("/proc/self/maps"):
+        if "libamdhip64" in line:
+            libs.add(line.split()[-1])
+    assert len(libs) == 1, libs
