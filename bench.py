@@ -92,6 +92,9 @@ def main():
     ap.add_argument("--workload", default="c2", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-queries", type=int, default=32)
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="first run three plain 1 GiB device-to-device copies (reference "
+                         "kernel of known size for scaling HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (queries shard "
@@ -106,6 +109,15 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.calibrate_copy:
+        src = torch.ones(1 << 27, dtype=torch.float64, device=dev)   # 1 GiB
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+        print("[bench] copy calibration: 3 x 1 GiB read + 1 GiB written", file=sys.stderr,
+              flush=True)
     X = torch.from_numpy(w.X).to(dev)
     Z = torch.from_numpy(w.Z).to(dev)
     fn = rrs.DEPTH_FUNCS[notion]
@@ -126,6 +138,7 @@ def main():
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     prof = rrs.rrs_profile_read()
+    counters = {c: rrs.rrs_profile_counter(c) for c in ("select_fast", "select_fallback")}
     rrs.rrs_profile_enable(False)
     depth = out["depth"].cpu().numpy()
 
@@ -174,6 +187,7 @@ def main():
         "cpu_baseline": cpu,
         "kernels": {k: {"avg_ms": v["avg_ms"], "launches_per_step": v["launches"] / args.steps,
                         "ms_per_step": v["total_ms"] / args.steps} for k, v in prof.items()},
+        "counters": counters,
         "depth_mean": float(depth.mean()),
     }
     print(json.dumps(line), flush=True)

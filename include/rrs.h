@@ -65,12 +65,20 @@ typedef enum {
     RRS_E_INTERNAL = 6
 } rrs_status;
 
-/* Arithmetic of the projection step.  RRS_F64: every projection is the
- * binary64 fused multiply-add chain over coordinates 0..d-1 of the shared
- * recipe, so counts, order statistics and depths are exact (bit-identical to
- * the FP64 oracle). */
+/* Arithmetic of the projection step.
+ * RRS_F64: every projection is the binary64 fused multiply-add chain over
+ *   coordinates 0..d-1 of the shared recipe, so counts, order statistics and
+ *   depths are exact (bit-identical to the FP64 oracle).
+ * RRS_BF16_RECHECK (halfspace depth only): projections on the matrix cores
+ *   from two-term bfloat16 splits of the mean-centred data and of the
+ *   directions (three products per K step, binary32 accumulation); a sign is
+ *   taken from that value only when it exceeds a rigorous error margin,
+ *   otherwise the pair is recomputed with the binary64 recipe.  The counts,
+ *   and therefore the depths and the RRS trajectory, are identical to
+ *   RRS_F64.  Requires ceil(K / n_refine) < 65536 and m <= 65535 queries. */
 typedef enum {
-    RRS_F64 = 0
+    RRS_F64 = 0,
+    RRS_BF16_RECHECK = 2
 } rrs_precision;
 
 typedef struct {
@@ -139,6 +147,12 @@ typedef struct {
 
 rrs_status rrs_profile_enable(int32_t on);
 int32_t rrs_profile_read(rrs_kernel_stat *out, int32_t max_entries);
+
+/* Event counters gathered while timing is on.  "select_fast": order-statistic
+ * pairs (median, MAD, MAD_+) resolved by the sampled bracket; "select_fallback":
+ * pairs resolved by the exact radix fallback.  Returns 0 and writes *value,
+ * or -1 for an unknown name or NULL pointer. */
+int32_t rrs_profile_counter(const char *name, double *value);
 
 /* Diagnostic for parity checks of the direction generator (step a1 alone):
  * writes the m_dir directions of refinement l (1-based) for the query whose

@@ -104,9 +104,9 @@ rrs_status ensure_arena(int dev, size_t need, void **out)
 
 // Optional per-kernel timing: HIP events recorded around every launch on the
 // launch stream, read back once the call has synchronised the stream.
-enum { K_GEN = 0, K_PROJ, K_SELECT, K_ARGMIN, K_OTHER, K_COUNT };
+enum { K_GEN = 0, K_PROJ, K_SELECT, K_ARGMIN, K_MFMA, K_OTHER, K_COUNT };
 const char *const kKernelNames[K_COUNT] = {"k_gen_dirs", "k_proj_f64", "k_select",
-                                           "k_argmin_pole", "k_misc"};
+                                           "k_argmin_pole", "k_gemm_sign", "k_misc"};
 struct ProfRec {
     int kind;
     hipEvent_t a, b;
@@ -120,6 +120,7 @@ struct Profiler {
     int64_t launches[K_COUNT] = {};
     double ms[K_COUNT] = {};
     double work[K_COUNT] = {};
+    double sel_fast = 0.0, sel_fallback = 0.0;
     hipEvent_t get()
     {
         if (used == pool.size()) {
@@ -187,7 +188,14 @@ rrs_status run(int notion, const double *X, int64_t n, int64_t d, const double *
     if (r < 1) return fail(RRS_E_INVAL, "n_refine must be >= 1 (got %d)", r);
     if (!(alpha > 0.0 && alpha <= 1.0))
         return fail(RRS_E_INVAL, "cap_shrink must be in (0, 1] (got %g)", alpha);
-    if (o.precision != RRS_F64) return fail(RRS_E_INVAL, "unknown precision %d", o.precision);
+    if (o.precision != RRS_F64 && o.precision != RRS_BF16_RECHECK)
+        return fail(RRS_E_INVAL, "unknown precision %d", o.precision);
+    const bool mfma = o.precision == RRS_BF16_RECHECK;
+    if (mfma && notion != rrs::NOTION_HALFSPACE)
+        return fail(RRS_E_INVAL, "precision RRS_BF16_RECHECK is available for halfspace depth only");
+    if (mfma && ((K + r - 1) / r >= 65536 || nq > 65535))
+        return fail(RRS_E_INVAL,
+                    "precision RRS_BF16_RECHECK needs ceil(K/n_refine) < 65536 directions");
     if (n > 0x7FFFFFFFLL || d > 0x7FFFFFFFLL)
         return fail(RRS_E_INVAL, "n and d must fit in 31 bits");
     if (o.query_offset < 0) return fail(RRS_E_INVAL, "query_offset must be >= 0");
@@ -215,19 +223,27 @@ rrs_status run(int notion, const double *X, int64_t n, int64_t d, const double *
         const size_t cap = (freeb - ((size_t)1 << 30)) / 10 * 8;
         if (limit > cap) limit = cap;
     }
+    // matrix-core form: split operands, K padded to 16, directions to 64
+    const int64_t kp = mfma ? rrs::mfma_kpad(d) : 0;
+    const int64_t ldb = (m + rrs::kMfmaCols - 1) / rrs::kMfmaCols * rrs::kMfmaCols;
     size_t per_q = (size_t)d * ldm * 8 + (size_t)d * 8 + 16;
     if (half)
         per_q += (size_t)ldm * 8;
     else
         per_q += (size_t)m * n * 8 + (size_t)ldm * 8;
+    if (mfma) per_q += (size_t)ldb * kp * 4 + (size_t)ldb * 4 + (size_t)m * n * 8 / 100;
     int64_t qb = (int64_t)(limit / per_q);
     if (qb < 1) qb = 1;
     if (qb > nq) qb = nq;
     if (qb > 65535) qb = 65535;
+    // recheck queue: 1% of the pairs of a launch, at least 1M entries
+    uint64_t qcap = (uint64_t)qb * (uint64_t)m * (uint64_t)n / 100;
+    if (qcap < (1u << 20)) qcap = 1u << 20;
+    if (qcap > 0xFFFFFFF0ull) qcap = 0xFFFFFFF0ull;
 
     // workspace layout
     const bool stage_in = !dev_ptrs;
-    size_t sizes[12];
+    size_t sizes[22];
     int k = 0;
     sizes[k++] = (size_t)d * ldx * 8;                          // XT
     sizes[k++] = stage_in ? (size_t)n * d * 8 : 0;             // X staging
@@ -242,6 +258,16 @@ rrs_status run(int notion, const double *X, int64_t n, int64_t d, const double *
     const bool want_trace = o.trace != nullptr, want_poles = o.poles != nullptr;
     sizes[k++] = stage_in ? (size_t)nq * (8 + 8 + (want_poles ? d * 8 : 0)) : 0;  // outputs
     sizes[k++] = (stage_in && want_trace) ? (size_t)nq * r * 3 * 8 : 0;         // trace
+    sizes[k++] = 64;                                                             // stats
+    sizes[k++] = mfma ? (size_t)d * 8 : 0;                                       // xbar
+    sizes[k++] = mfma ? (size_t)n * kp * 2 : 0;                                  // Ahi
+    sizes[k++] = mfma ? (size_t)n * kp * 2 : 0;                                  // Alo
+    sizes[k++] = mfma ? (size_t)n * 4 : 0;                                       // anorm
+    sizes[k++] = mfma ? (size_t)qb * ldb * kp * 2 : 0;                           // Bhi
+    sizes[k++] = mfma ? (size_t)qb * ldb * kp * 2 : 0;                           // Blo
+    sizes[k++] = mfma ? (size_t)qb * ldb * 4 : 0;                                // cmarg
+    sizes[k++] = mfma ? (size_t)qcap * 8 : 0;                                    // queue
+    sizes[k++] = 64;                                                             // qcount, flag
     void *base = nullptr;
     rrs_status s = ensure_arena(dev, carve_size(sizes, k), &base);
     if (s != RRS_OK) return s;
@@ -260,6 +286,17 @@ rrs_status run(int notion, const double *X, int64_t n, int64_t d, const double *
     int64_t *out_count = cv.take<int64_t>(stage_in ? (size_t)nq : 0);
     double *out_poles = cv.take<double>((stage_in && want_poles) ? (size_t)nq * d : 0);
     int64_t *out_trace = cv.take<int64_t>((stage_in && want_trace) ? (size_t)nq * r * 3 : 0);
+    uint32_t *stats = cv.take<uint32_t>(16);
+    double *xbar = cv.take<double>(mfma ? (size_t)d : 0);
+    __bf16 *Ahi = cv.take<__bf16>(mfma ? (size_t)n * kp : 0);
+    __bf16 *Alo = cv.take<__bf16>(mfma ? (size_t)n * kp : 0);
+    float *anorm = cv.take<float>(mfma ? (size_t)n : 0);
+    __bf16 *Bhi = cv.take<__bf16>(mfma ? (size_t)qb * ldb * kp : 0);
+    __bf16 *Blo = cv.take<__bf16>(mfma ? (size_t)qb * ldb * kp : 0);
+    float *cmarg = cv.take<float>(mfma ? (size_t)qb * ldb : 0);
+    uint64_t *queue = cv.take<uint64_t>(mfma ? (size_t)qcap : 0);
+    uint32_t *qctl = cv.take<uint32_t>(16);  // [0] queue length, [1] overflow flag
+    if (g_prof.on) HIP_TRY(rrs::launch_fill_u32(stats, 16, 0u, st));
 
     const double *Xd = X, *Zd = Z;
     double *depth_d = depth;
@@ -277,6 +314,7 @@ rrs_status run(int notion, const double *X, int64_t n, int64_t d, const double *
         trace_d = want_trace ? out_trace : nullptr;
     }
     HIP_TRY(rrs::launch_transpose(Xd, n, d, ldx, XT, st));
+    if (mfma) HIP_TRY(rrs::launch_mfma_prep(Xd, n, d, xbar, Ahi, Alo, anorm, st));
     // zero the direction padding once (the generator writes j < m only)
     HIP_TRY(rrs::launch_fill_u32((uint32_t *)UT, qb * d * ldm * 2, 0u, st));
 
@@ -292,8 +330,23 @@ rrs_status run(int notion, const double *X, int64_t n, int64_t d, const double *
                 ProfScope ps(K_GEN, (double)nb * m * d, st);
                 HIP_TRY(rrs::launch_gen_dirs(ga, st));
             }
-            rrs::ProjArgs pa{XT, ldx, n, d, Zd + q0 * d, UT, ldm, m, nb, cnt, T};
-            if (half) {
+            rrs::ProjArgs pa{XT, ldx, n, d, Zd + q0 * d, UT, ldm, m, nb, cnt, T, nullptr};
+            if (half && mfma) {
+                HIP_TRY(rrs::launch_fill_u32(cnt, nb * ldm * 2, 0u, st));
+                HIP_TRY(rrs::launch_fill_u32(qctl, 16, 0u, st));
+                HIP_TRY(rrs::launch_mfma_dirs(UT, d, m, ldm, ldb, nb, Zd + q0 * d, xbar, Bhi, Blo,
+                                              cmarg, st));
+                rrs::MfmaArgs ma{Ahi,  Alo,    anorm, n,    d,      Bhi,     Blo,
+                                 cmarg, m,     ldm,   ldb,  nb,     cnt,     queue,
+                                 qctl, qcap,   qctl + 1, Xd, Zd + q0 * d, UT};
+                {
+                    ProfScope ps(K_MFMA, proj_units, st);
+                    HIP_TRY(rrs::launch_mfma_count(ma, st));
+                }
+                // queue overflow (never expected): recount in binary64
+                pa.only_if = qctl + 1;
+                HIP_TRY(rrs::launch_proj_f64(pa, true, st));
+            } else if (half) {
                 HIP_TRY(rrs::launch_fill_u32(cnt, nb * ldm * 2, 0u, st));
                 ProfScope ps(K_PROJ, proj_units, st);
                 HIP_TRY(rrs::launch_proj_f64(pa, true, st));
@@ -302,9 +355,12 @@ rrs_status run(int notion, const double *X, int64_t n, int64_t d, const double *
                     ProfScope ps(K_PROJ, proj_units, st);
                     HIP_TRY(rrs::launch_proj_f64(pa, false, st));
                 }
-                rrs::SelectArgs sa{T, n, m, ldm, nb, Dj};
+                rrs::SelectArgs sa{T, n, m, ldm, nb, Dj, g_prof.on ? stats : nullptr};
                 ProfScope ps(K_SELECT, proj_units, st);
-                HIP_TRY(rrs::launch_select(sa, notion, lds, st));
+                if (n <= rrs::select_reg_max_n())
+                    HIP_TRY(rrs::launch_select_reg(sa, notion, st));
+                else
+                    HIP_TRY(rrs::launch_select(sa, notion, lds, st));
             }
             rrs::ArgminArgs aa{m, ldm, d, nb, cnt, Dj, UT, pole, best_d, best_c,
                                trace_d ? trace_d + q0 * r * 3 : nullptr, l, r};
@@ -330,7 +386,13 @@ rrs_status run(int notion, const double *X, int64_t n, int64_t d, const double *
                                    hipMemcpyDeviceToHost, st));
     }
     HIP_TRY(hipStreamSynchronize(st));
-    if (g_prof.on) prof_collect();
+    if (g_prof.on) {
+        prof_collect();
+        uint32_t hs[2] = {0, 0};
+        HIP_TRY(hipMemcpy(hs, stats, sizeof(hs), hipMemcpyDeviceToHost));
+        g_prof.sel_fast += hs[0];
+        g_prof.sel_fallback += hs[1];
+    }
     return RRS_OK;
 }
 
@@ -395,7 +457,24 @@ rrs_status rrs_profile_enable(int32_t on)
         g_prof.ms[k] = 0.0;
         g_prof.work[k] = 0.0;
     }
+    g_prof.sel_fast = 0.0;
+    g_prof.sel_fallback = 0.0;
     return RRS_OK;
+}
+
+int32_t rrs_profile_counter(const char *name, double *value)
+{
+    std::lock_guard<std::mutex> lock(g_mutex);
+    if (!name || !value) return -1;
+    if (std::strcmp(name, "select_fast") == 0) {
+        *value = g_prof.sel_fast;
+        return 0;
+    }
+    if (std::strcmp(name, "select_fallback") == 0) {
+        *value = g_prof.sel_fallback;
+        return 0;
+    }
+    return -1;
 }
 
 int32_t rrs_profile_read(rrs_kernel_stat *out, int32_t max_entries)

@@ -164,8 +164,10 @@ template <int JT, bool COUNT>
 __global__ __launch_bounds__(256) void k_proj_f64(
     const double *__restrict__ XT, int64_t ldx, int64_t n, int64_t d,
     const double *__restrict__ Zb, const double *__restrict__ UT, int64_t ldm, int64_t m,
-    uint32_t *__restrict__ cnt, double *__restrict__ T, int64_t pts_per_block)
+    uint32_t *__restrict__ cnt, double *__restrict__ T, int64_t pts_per_block,
+    const uint32_t *__restrict__ only_if)
 {
+    if (only_if && *only_if == 0u) return;  // conditional launch (whole grid exits)
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
     const int64_t qi = blockIdx.y;
@@ -649,10 +651,10 @@ hipError_t launch_proj_f64(const ProjArgs &a, bool count_mode, hipStream_t st)
     dim3 grid(gx, (unsigned)a.qb, (unsigned)chunks);
     if (count_mode)
         hipLaunchKernelGGL((k_proj_f64<JT, true>), grid, dim3(256), 0, st, a.XT, a.ldx, a.n, a.d,
-                           a.Z, a.UT, a.ldm, a.m, a.cnt, a.T, per);
+                           a.Z, a.UT, a.ldm, a.m, a.cnt, a.T, per, a.only_if);
     else
         hipLaunchKernelGGL((k_proj_f64<JT, false>), grid, dim3(256), 0, st, a.XT, a.ldx, a.n,
-                           a.d, a.Z, a.UT, a.ldm, a.m, a.cnt, a.T, per);
+                           a.d, a.Z, a.UT, a.ldm, a.m, a.cnt, a.T, per, a.only_if);
     return hipGetLastError();
 }
 

@@ -27,12 +27,32 @@ struct ProjArgs {
     int64_t ldm, m, qb;
     uint32_t *cnt;
     double *T;
+    const uint32_t *only_if;  // count mode: run only when *only_if != 0 (may be null)
+};
+
+// Halfspace counts on matrix cores (rrs_mfma.hip).
+struct MfmaArgs {
+    const __bf16 *Ahi, *Alo;   // [n][kp] centred data, two bf16 terms
+    const float *anorm;        // [n] norm bound of the centred points
+    int64_t n, d;
+    const __bf16 *Bhi, *Blo;   // [qb][ldb][kp] split directions + centring
+    const float *cmarg;        // [qb][ldb] direction part of the margin
+    int64_t m, ldm, ldb, qb;
+    uint32_t *cnt;             // [qb][ldm][2]
+    uint64_t *queue;           // uncertain (query, direction, point)
+    uint32_t *qcount;
+    uint64_t qcap;
+    uint32_t *flag;            // set when the queue overflowed
+    const double *X;           // [n][d] binary64 data (recheck)
+    const double *Z;           // [qb][d] queries of the batch
+    const double *UT;          // [qb][d][ldm] binary64 directions
 };
 
 struct SelectArgs {
     const double *T;
     int64_t n, m, ldm, qb;
     double *Dj;
+    uint32_t *stats;  // optional [2]: pairs resolved by the bracket / the fallback
 };
 
 struct ArgminArgs {
@@ -54,7 +74,18 @@ hipError_t launch_fill_u32(uint32_t *p, int64_t count, uint32_t v, hipStream_t s
 hipError_t launch_proj_f64(const ProjArgs &a, bool count_mode, hipStream_t st);
 int64_t select_lds_max_n(int device);
 hipError_t launch_select(const SelectArgs &a, int notion, bool lds, hipStream_t st);
+int64_t select_reg_max_n();
+hipError_t launch_select_reg(const SelectArgs &a, int notion, hipStream_t st);
 hipError_t launch_argmin(const ArgminArgs &a, bool half, hipStream_t st);
+int64_t mfma_kpad(int64_t d);
+void mfma_margins(int64_t d, int64_t kp, double *kappa, double *canon);
+hipError_t launch_mfma_prep(const double *X, int64_t n, int64_t d, double *xbar, __bf16 *Ahi,
+                            __bf16 *Alo, float *anorm, hipStream_t st);
+hipError_t launch_mfma_dirs(const double *UT, int64_t d, int64_t m, int64_t ldm, int64_t ldb,
+                            int64_t qb, const double *Zb, const double *xbar, __bf16 *Bhi,
+                            __bf16 *Blo, float *cmarg, hipStream_t st);
+hipError_t launch_mfma_count(const MfmaArgs &a, hipStream_t st);
+constexpr int kMfmaCols = 64;  // directions per matrix-core workgroup
 hipError_t launch_init_state(int64_t qb, int64_t d, int64_t n, double *pole, double *best_d,
                              int64_t *best_c, hipStream_t st);
 hipError_t launch_finalize(int64_t qb, int64_t d, int64_t n, bool half, const double *pole,

@@ -17,14 +17,14 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "librrs.so")
 
 RRS_OK, RRS_E_INVAL, RRS_E_NOMEM, RRS_E_DEVICE, RRS_E_INTERNAL = 0, 1, 2, 3, 6
-RRS_F64 = 0
-PRECISIONS = {"f64": RRS_F64}
+RRS_F64, RRS_BF16_RECHECK = 0, 2
+PRECISIONS = {"f64": RRS_F64, "bf16": RRS_BF16_RECHECK}
 STATUS_NAMES = {0: "RRS_OK", 1: "RRS_E_INVAL", 2: "RRS_E_NOMEM", 3: "RRS_E_DEVICE",
                 6: "RRS_E_INTERNAL"}
 
 EXPORTED = ["rrs_depth_halfspace", "rrs_depth_projection", "rrs_depth_apd",
             "rrs_last_error", "rrs_release_workspace", "rrs_version", "rrs_debug_directions",
-            "rrs_profile_enable", "rrs_profile_read"]
+            "rrs_profile_enable", "rrs_profile_read", "rrs_profile_counter"]
 
 
 class RRSError(RuntimeError):
@@ -88,6 +88,8 @@ def load(path: str = LIB_PATH):
     L.rrs_profile_enable.restype = ctypes.c_int
     L.rrs_profile_read.argtypes = [ctypes.POINTER(rrs_kernel_stat), i32]
     L.rrs_profile_read.restype = i32
+    L.rrs_profile_counter.argtypes = [ctypes.c_char_p, ctypes.POINTER(ctypes.c_double)]
+    L.rrs_profile_counter.restype = i32
     _lib = L
     return L
 
@@ -243,3 +245,10 @@ def rrs_profile_read() -> dict:
                                 "avg_ms": float(e.total_ms) / max(int(e.launches), 1),
                                 "work_units": float(e.work_units)}
     return out
+
+
+def rrs_profile_counter(name: str):
+    """Value of a diagnostic event counter (None if unknown)."""
+    v = ctypes.c_double()
+    rc = load().rrs_profile_counter(name.encode(), ctypes.byref(v))
+    return float(v.value) if rc == 0 else None

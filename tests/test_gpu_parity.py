@@ -187,3 +187,64 @@ def test_single_hip_runtime_in_process():
         if "libamdhip64" in line:
             libs.add(line.split()[-1])
     assert len(libs) == 1, libs
+
+
+# --------------------------------------------------------------------------
+# Halfspace depth on the matrix cores (bf16 split + binary64 recheck): the
+# counts, poles and traces must be identical to the binary64 recipe.
+# --------------------------------------------------------------------------
+def test_bf16_c1_halfspace():
+    w = workloads.make("c1")
+    _compare("halfspace", w, precision="bf16")
+
+
+@pytest.mark.parametrize("n,d,law", [(700, 2, "gaussian"), (1001, 3, "integer"),
+                                     (1500, 7, "exponential"), (900, 33, "mixture"),
+                                     (2100, 100, "toeplitz")])
+def test_bf16_halfspace_parity(n, d, law):
+    w = workloads.small("halfspace", n, d, 20, 240, 6, 0.5, law=law, seed_cfg=n + 3 * d)
+    _compare("halfspace", w, precision="bf16")
+
+
+def test_bf16_halfspace_ties_and_far_queries():
+    w = workloads.small("halfspace", 300, 4, 16, 160, 4, 0.5, law="integer", seed_cfg=78)
+    Z = w.Z.copy()
+    Z[:6] = w.X[:6]
+    Z[6] = 1e4
+    w.Z = Z
+    X = w.X.copy()
+    X[100:140] = X[0]
+    w.X = X
+    _compare("halfspace", w, precision="bf16")
+
+
+def test_bf16_matches_f64_on_c1b_and_offset_data():
+    w = workloads.make("c1b")
+    _compare("halfspace", w, precision="bf16")
+    # data far from the origin: the centring by the mean keeps the margin small
+    w2 = workloads.small("halfspace", 800, 5, 12, 200, 5, 0.6, law="gaussian", seed_cfg=9)
+    w2.X = w2.X + 1e3
+    w2.Z = w2.Z + 1e3
+    _compare("halfspace", w2, precision="bf16")
+
+
+def test_bf16_rejected_for_projection():
+    w = workloads.small("projection", 100, 3, 2, 20, 2, 0.5)
+    with pytest.raises(rrs.RRSError):
+        rrs.rrs_depth_projection(w.X, w.Z, w.K, w.n_refine, w.cap_shrink, precision="bf16")
+
+
+def test_select_fast_path_dominates_on_centred_columns():
+    """Queries at the centre of the data make the projection medians straddle
+    zero; the bracketed select must still resolve almost every order
+    statistic without the radix fallback (results are exact either way)."""
+    w = workloads.small("projection", 4096, 8, 16, 400, 4, 0.5, law="gaussian", seed_cfg=12)
+    w.Z = w.Z * 0.01
+    rrs.rrs_profile_enable(True)
+    got = rrs.rrs_depth_projection(w.X, w.Z, w.K, w.n_refine, w.cap_shrink, 0)["depth"]
+    fast = rrs.rrs_profile_counter("select_fast")
+    fb = rrs.rrs_profile_counter("select_fallback")
+    rrs.rrs_profile_enable(False)
+    ref = oracle.rrs_depth("projection", w.X, w.Z, w.K, w.n_refine, w.cap_shrink, 0)["depth"]
+    assert np.array_equal(got, ref)
+    assert fast > 0 and fb / (fast + fb) < 0.02, (fast, fb)
