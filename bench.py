@@ -28,6 +28,7 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
 FP64_VALU_PEAK_TFLOPS = 78.6   # 256 CU x 4 SIMD x 16 lanes x 2 flop x 2.4 GHz
+MFMA_PEAK_TFLOPS = {"bf16": 2500.0, "f32": 157.3, "f32_plain": 157.3}   # dense matrix cores
 
 WORKLOADS = {
     "c2": ("c2", "projection"),
@@ -39,8 +40,18 @@ WORKLOADS = {
 }
 
 
-def kernel_model(name: str, notion: str, d: int):
-    """Algorithmic cost per work unit of each kernel."""
+def kernel_model(name: str, notion: str, d: int, precision: str = "f64"):
+    """Algorithmic cost per work unit of each kernel (bytes or flops the method needs)."""
+    if name == "k_gemm_sign":
+        # one projection is a d-term dot product: 2d flops, whatever the
+        # padding of K and the number of split products the kernel issues
+        kp = (d + 2 + 15) // 16 * 16 if precision == "bf16" else (d + 1 + 7) // 8 * 8
+        issued = 2 * kp * (3 if precision == "bf16" else 1)
+        return {"bound": "mfma", "per_unit": 2.0 * d, "unit": "TFLOP/s",
+                "peak": MFMA_PEAK_TFLOPS[precision], "scale": 1e-12,
+                "what": f"2d = {2 * d} algorithmic flops per projection "
+                        f"({issued} matrix-core flops issued)",
+                "issued_per_unit": float(issued)}
     if name == "k_proj_f64":
         if notion == "halfspace":
             return {"bound": "alu", "per_unit": 2.0 * d, "unit": "TFLOP/s",
@@ -64,7 +75,11 @@ def cpu_model() -> str:
     return "unknown"
 
 
-def cpu_baseline(w, notion, max_queries):
+def cpu_baseline(w, notion, max_queries, per_thread_budget=1.2e8):
+    """The FP64 oracle on a bounded sample of the workload: whole queries when
+    one query costs at most `per_thread_budget` projections, else only the
+    first refinement (the m sphere directions of l = 1) of each sampled query,
+    which is the same per-projection work."""
     import numpy as np
 
     import oracle
@@ -72,15 +87,17 @@ def cpu_baseline(w, notion, max_queries):
     threads = oracle.max_threads()
     nq = max(1, min(threads, max_queries, w.nq))
     qs = np.arange(nq)
+    full = w.n_refine * w.m_dirs * w.n <= per_thread_budget
+    K, r = (w.K, w.n_refine) if full else (w.m_dirs, 1)
     t0 = time.perf_counter()
-    oracle.rrs_depth_idx(notion, w.X, w.Z[qs], qs, w.K, w.n_refine, w.cap_shrink, w.rrs_seed,
-                         nthreads=nq)
+    oracle.rrs_depth_idx(notion, w.X, w.Z[qs], qs, K, r, w.cap_shrink, w.rrs_seed, nthreads=nq)
     dt = time.perf_counter() - t0
-    proj = nq * w.n_refine * w.m_dirs * w.n
+    proj = nq * r * w.m_dirs * w.n
+    what = (f"all {w.n_refine} refinements ({w.n_refine * w.m_dirs} directions each)" if full
+            else f"refinement 1 only ({w.m_dirs} sphere directions each)")
     return {"value": proj / dt, "unit": "projections/s", "cores": int(nq), "kind": "oracle",
-            "sample": f"queries 0..{nq - 1} of {w.nq} (all {w.n_refine} refinements, "
-                      f"{w.n_refine * w.m_dirs} directions each), one OpenMP thread per "
-                      f"query, {dt:.1f} s wall on {cpu_model()}",
+            "sample": f"queries 0..{nq - 1} of {w.nq}, {what}, one OpenMP thread per query, "
+                      f"{proj:.3g} projections in {dt:.1f} s wall on {cpu_model()}",
             "seconds": dt}
 
 
@@ -90,6 +107,8 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="c2", choices=sorted(WORKLOADS))
+    ap.add_argument("--precision", default="f64", choices=["f64", "f32", "bf16", "f32_plain"],
+                    help="projection arithmetic (matrix-core forms: halfspace depth only)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-queries", type=int, default=32)
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -98,7 +117,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (queries shard "
-              f"across GPUs without communication, see DESIGN.md)", file=sys.stderr)
+              f"across GPUs without communication; run one process per GPU)", file=sys.stderr)
         sys.exit(2)
 
     import torch
@@ -122,10 +141,12 @@ def main():
     Z = torch.from_numpy(w.Z).to(dev)
     fn = rrs.DEPTH_FUNCS[notion]
     print(f"[bench] workload {args.workload} ({notion}) n={w.n} d={w.d} queries={w.nq} "
-          f"K={w.K} r={w.n_refine} alpha={w.cap_shrink}", file=sys.stderr, flush=True)
+          f"K={w.K} r={w.n_refine} alpha={w.cap_shrink} precision={args.precision}",
+          file=sys.stderr, flush=True)
+    prec = {"precision": args.precision}
 
     for i in range(args.warmup):
-        fn(X, Z, w.K, w.n_refine, w.cap_shrink, w.rrs_seed)
+        fn(X, Z, w.K, w.n_refine, w.cap_shrink, w.rrs_seed, **prec)
         torch.cuda.synchronize()
         print(f"[bench] warmup {i + 1}/{args.warmup} done", file=sys.stderr, flush=True)
 
@@ -133,12 +154,13 @@ def main():
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for i in range(args.steps):
-        out = fn(X, Z, w.K, w.n_refine, w.cap_shrink, w.rrs_seed)
+        out = fn(X, Z, w.K, w.n_refine, w.cap_shrink, w.rrs_seed, **prec)
         print(f"[bench] step {i + 1}/{args.steps}", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     prof = rrs.rrs_profile_read()
-    counters = {c: rrs.rrs_profile_counter(c) for c in ("select_fast", "select_fallback")}
+    counters = {c: rrs.rrs_profile_counter(c)
+                for c in ("select_fast", "select_fallback", "recheck_pairs")}
     rrs.rrs_profile_enable(False)
     depth = out["depth"].cpu().numpy()
 
@@ -151,7 +173,7 @@ def main():
     dom = max(prof.items(), key=lambda kv: kv[1]["total_ms"]) if prof else None
     if dom is not None:
         name, st = dom
-        model = kernel_model(name, notion, w.d)
+        model = kernel_model(name, notion, w.d, args.precision)
         if model is not None:
             units_per_launch = st["work_units"] / st["launches"]
             achieved = model["per_unit"] * units_per_launch / (st["avg_ms"] * 1e-3) * model["scale"]
@@ -159,6 +181,9 @@ def main():
                     "peak": model["peak"], "unit": model["unit"], "frac": achieved / model["peak"],
                     "traffic": None, "avg_launch_ms": st["avg_ms"],
                     "units_per_launch": units_per_launch, "per_unit": model["what"]}
+            if "issued_per_unit" in model:
+                roof["issued_frac"] = (model["issued_per_unit"] * units_per_launch
+                                       / (st["avg_ms"] * 1e-3) * 1e-12 / model["peak"])
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -176,12 +201,14 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": {"f64": "f64", "f32": "f32", "f32_plain": "f32",
+                  "bf16": "bf16"}[args.precision],
         "data": "synthetic",
         "config": {"workload": f"{args.workload}: {notion} depth, {w.recipe}; K={w.K}, "
                                f"n_refine={w.n_refine}, cap_shrink={w.cap_shrink}",
                    "notion": notion, "n": w.n, "d": w.d, "queries": w.nq, "K": w.K,
-                   "n_refine": w.n_refine, "cap_shrink": w.cap_shrink, "precision": "f64",
+                   "n_refine": w.n_refine, "cap_shrink": w.cap_shrink,
+                   "precision": args.precision,
                    "projections_per_step": proj},
         "roofline": roof,
         "cpu_baseline": cpu,

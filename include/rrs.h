@@ -62,6 +62,8 @@ typedef enum {
     RRS_E_INVAL = 1,
     RRS_E_NOMEM = 2,
     RRS_E_DEVICE = 3,
+    RRS_E_BUSY = 4,       /* rrs_wait timed out */
+    RRS_E_CANCELLED = 5,  /* the request's context was destroyed before it ran */
     RRS_E_INTERNAL = 6
 } rrs_status;
 
@@ -69,16 +71,25 @@ typedef enum {
  * RRS_F64: every projection is the binary64 fused multiply-add chain over
  *   coordinates 0..d-1 of the shared recipe, so counts, order statistics and
  *   depths are exact (bit-identical to the FP64 oracle).
- * RRS_BF16_RECHECK (halfspace depth only): projections on the matrix cores
- *   from two-term bfloat16 splits of the mean-centred data and of the
- *   directions (three products per K step, binary32 accumulation); a sign is
+ * RRS_F32_RECHECK (halfspace depth only): projections of the mean-centred
+ *   data on the matrix cores in binary32 (v_mfma_f32_32x32x2_f32); a sign is
  *   taken from that value only when it exceeds a rigorous error margin,
- *   otherwise the pair is recomputed with the binary64 recipe.  The counts,
- *   and therefore the depths and the RRS trajectory, are identical to
- *   RRS_F64.  Requires ceil(K / n_refine) < 65536 and m <= 65535 queries. */
+ *   otherwise the pair is recomputed with the binary64 recipe.  Counts,
+ *   depths and the RRS trajectory are identical to RRS_F64.
+ * RRS_BF16_RECHECK (halfspace depth only): as RRS_F32_RECHECK, with the
+ *   products from two-term bfloat16 splits of the centred data and of the
+ *   directions (three bf16 products per K step, binary32 accumulation).
+ *   Identical to RRS_F64.
+ * RRS_F32_PLAIN (halfspace depth only): the binary32 matrix-core projection
+ *   decides every sign by itself (a zero counts on both sides), without
+ *   recheck; counts may differ from RRS_F64 where |t| is within the binary32
+ *   rounding error, and the trajectory may then differ too.
+ * The matrix-core forms need ceil(K / n_refine) < 65536 and m <= 65535. */
 typedef enum {
     RRS_F64 = 0,
-    RRS_BF16_RECHECK = 2
+    RRS_F32_RECHECK = 1,
+    RRS_BF16_RECHECK = 2,
+    RRS_F32_PLAIN = 3
 } rrs_precision;
 
 typedef struct {
@@ -136,8 +147,9 @@ int32_t rrs_version(void);
  * copies up to max_entries totals (one per kernel that ran) into out and
  * returns how many it wrote (out may be NULL to count them).  work_units is
  * the sum over launches of the units each launch processed: projections
- * (query x direction x point) for k_proj_f64 and k_select, coordinates for
- * k_gen_dirs, directions for k_argmin_pole. */
+ * (query x direction x point) for k_proj_f64, k_select and k_gemm_sign,
+ * coordinates for k_gen_dirs, directions for k_argmin_pole (0 for k_recheck,
+ * which handles the pairs the matrix-core forms left uncertain). */
 typedef struct {
     char name[32];
     int64_t launches;
@@ -150,9 +162,88 @@ int32_t rrs_profile_read(rrs_kernel_stat *out, int32_t max_entries);
 
 /* Event counters gathered while timing is on.  "select_fast": order-statistic
  * pairs (median, MAD, MAD_+) resolved by the sampled bracket; "select_fallback":
- * pairs resolved by the exact radix fallback.  Returns 0 and writes *value,
- * or -1 for an unknown name or NULL pointer. */
+ * pairs resolved by the exact radix fallback; "recheck_pairs": (query,
+ * direction, point) projections the matrix-core forms recomputed in binary64.
+ * Returns 0 and writes *value, or -1 for an unknown name or NULL pointer. */
 int32_t rrs_profile_counter(const char *name, double *value);
+
+/* ------------------------------------------------------------------------
+ * Serving: resident data sets and continuously batched requests.
+ *
+ * A context owns a slice of one device's memory (hbm_budget bytes, taken at
+ * creation and sub-allocated by the library), `slots` HIP streams and one
+ * scheduler thread.  Data sets are copied into the context once and stay
+ * resident until released.  rrs_submit copies the queries and returns at
+ * once; the scheduler admits pending requests in arrival order whenever a
+ * slot and enough of the budget are free (a request that does not fit yet is
+ * passed over by smaller later ones, at most 8 times, then admission waits
+ * for it), and each admitted request runs on its own stream, overlapping on
+ * the device with the others.  A request's result depends only on its own
+ * arguments (data set, queries, query_offset, K, n_refine, cap_shrink, seed,
+ * notion, precision): never on the other requests in flight.
+ * ------------------------------------------------------------------------ */
+typedef struct rrs_ctx rrs_ctx;
+typedef struct rrs_dataset rrs_dataset;
+typedef struct rrs_request rrs_request;
+
+typedef struct {
+    int32_t device;          /* HIP device ordinal */
+    int32_t slots;           /* requests running at once (one stream each); 0: 4 */
+    size_t hbm_budget;       /* device bytes for data sets and requests; 0: half
+                                of the free memory */
+    size_t request_ws_limit; /* workspace cap of one request (its queries are
+                                batched to fit); 0: hbm_budget / (2 slots) */
+} rrs_ctx_config;
+
+/* Creates a context (cfg may be NULL for the defaults).  RRS_E_NOMEM when
+ * the budget cannot be allocated, RRS_E_INVAL for a bad device or sizes. */
+rrs_status rrs_ctx_create(const rrs_ctx_config *cfg, rrs_ctx **out);
+/* Cancels pending requests (their rrs_wait returns RRS_E_CANCELLED), waits
+ * for the running ones, releases every data set and the budget.  Request
+ * handles stay valid for rrs_wait. */
+rrs_status rrs_ctx_destroy(rrs_ctx *ctx);
+
+/* Copies X (n x d row-major binary64, host memory) into the context and
+ * prepares it; the caller keeps X.  RRS_E_NOMEM when it does not fit the
+ * budget next to the resident data. */
+rrs_status rrs_dataset_put(rrs_ctx *ctx, const double *X, int64_t n, int64_t d,
+                           rrs_dataset **out);
+/* Releases a data set; its memory returns to the budget once the requests
+ * that use it have finished.  The handle is invalid afterwards. */
+rrs_status rrs_dataset_release(rrs_ctx *ctx, rrs_dataset *ds);
+
+/* Submits the depth (notion 0: halfspace, 1: projection, 2: asymmetric
+ * projection) of the m queries Z (host, m x d, copied before return) on the
+ * data set.  K, n_refine, cap_shrink, seed as for the synchronous calls;
+ * opts (may be NULL) supplies precision, query_offset and workspace_limit --
+ * device_ptrs, stream, poles and trace must be 0 / NULL.  RRS_E_NOMEM when
+ * the request could never fit the budget; RRS_E_INVAL as the synchronous
+ * calls. */
+rrs_status rrs_submit(rrs_ctx *ctx, rrs_dataset *ds, int32_t notion, const double *Z, int64_t m,
+                      int64_t K, int32_t n_refine, double cap_shrink, uint64_t seed,
+                      const rrs_opts *opts, rrs_request **out);
+
+/* Timestamps of a request in seconds of the host's monotonic clock
+ * (CLOCK_MONOTONIC): submitted, admitted to a slot, result in host memory. */
+typedef struct {
+    double submit_s, admit_s, done_s;
+    int64_t projections;     /* m x n_refine x ceil(K / n_refine) x n */
+    size_t bytes;            /* device memory the request held while running */
+} rrs_request_info;
+
+/* Waits up to timeout_s seconds (< 0: no limit) for the request.  On
+ * completion writes depth [m] (and count [m] for halfspace when count is not
+ * NULL, and *info when info is not NULL), frees the request and returns its
+ * status; on time-out returns RRS_E_BUSY and the handle stays valid. */
+rrs_status rrs_wait(rrs_request *req, double timeout_s, double *depth, int64_t *count,
+                    rrs_request_info *info);
+
+typedef struct {
+    int64_t pending, running, completed, failed;
+    int64_t datasets;
+    size_t bytes_in_use, bytes_peak, budget;
+} rrs_ctx_stats;
+rrs_status rrs_ctx_get_stats(rrs_ctx *ctx, rrs_ctx_stats *out);
 
 /* Diagnostic for parity checks of the direction generator (step a1 alone):
  * writes the m_dir directions of refinement l (1-based) for the query whose

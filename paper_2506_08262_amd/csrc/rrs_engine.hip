@@ -1,0 +1,359 @@
+// rrs_engine.hip -- planning and enqueueing of one RRS depth job.
+//
+// For each batch of queries the job runs the refinement loop of Alg. 4 /
+// Alg. S5 -- directions, projection, univariate depth, argmin and pole
+// update -- on one HIP stream.  The refinement chain stays on the device; the
+// host only enqueues kernels.
+#include "rrs_engine.hpp"
+
+#include <cstdarg>
+#include <cstdio>
+
+namespace rrs {
+
+namespace {
+thread_local std::string t_last_error;
+}
+
+std::string &last_error() { return t_last_error; }
+
+rrs_status fail(rrs_status s, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    t_last_error = buf;
+    return s;
+}
+
+size_t carve_size(const size_t *sizes, int k)
+{
+    size_t off = 0;
+    for (int i = 0; i < k; ++i) {
+        off = (off + 255) & ~(size_t)255;
+        off += sizes[i];
+    }
+    return off + 256;
+}
+
+const char *const kKernelNames[K_COUNT] = {"k_gen_dirs",    "k_proj_f64",  "k_select",
+                                           "k_argmin_pole", "k_gemm_sign", "k_recheck",
+                                           "k_misc"};
+
+hipEvent_t Profiler::get()
+{
+    if (used == pool.size()) {
+        hipEvent_t e;
+        if (hipEventCreate(&e) != hipSuccess) return nullptr;
+        pool.push_back(e);
+    }
+    return pool[used++];
+}
+
+void Profiler::collect()
+{
+    for (const Rec &r : recs) {
+        float t = 0.f;
+        if (hipEventElapsedTime(&t, r.a, r.b) == hipSuccess) {
+            launches[r.kind] += 1;
+            ms[r.kind] += t;
+            work[r.kind] += r.work;
+        }
+    }
+    recs.clear();
+    used = 0;
+}
+
+void Profiler::clear()
+{
+    recs.clear();
+    used = 0;
+    for (int k = 0; k < K_COUNT; ++k) {
+        launches[k] = 0;
+        ms[k] = 0.0;
+        work[k] = 0.0;
+    }
+    sel_fast = sel_fallback = recheck_pairs = 0.0;
+}
+
+namespace {
+
+// HIP events around one launch on its stream (when profiling).
+struct ProfScope {
+    Profiler *p;
+    Profiler::Rec rec{};
+    hipStream_t st;
+    bool live = false;
+    ProfScope(Profiler *prof, int kind, double work, hipStream_t s) : p(prof), st(s)
+    {
+        if (!p || !p->on) return;
+        rec.kind = kind;
+        rec.work = work;
+        rec.a = p->get();
+        rec.b = p->get();
+        if (rec.a && rec.b && hipEventRecord(rec.a, st) == hipSuccess) live = true;
+    }
+    ~ProfScope()
+    {
+        if (live && hipEventRecord(rec.b, st) == hipSuccess) p->recs.push_back(rec);
+    }
+};
+
+}  // namespace
+
+size_t data_bytes(int64_t n, int64_t d, int prec)
+{
+    const int64_t ldx = (n + 511) / 512 * 512;
+    size_t sizes[5] = {(size_t)d * ldx * 8, 0, 0, 0, 0};
+    if (prec >= 0) {
+        const int64_t kp = mfma_kpad(prec, d);
+        const size_t eb = mfma_elem_bytes(prec);
+        sizes[1] = (size_t)d * 8;
+        sizes[2] = (size_t)n * kp * eb;
+        sizes[3] = mfma_terms(prec) == 2 ? (size_t)n * kp * eb : 0;
+        sizes[4] = (size_t)n * 4;
+    }
+    return carve_size(sizes, 5);
+}
+
+hipError_t data_prepare(DataDev &D, void *mem, int prec, hipStream_t st)
+{
+    const int64_t n = D.n, d = D.d;
+    D.ldx = (n + 511) / 512 * 512;
+    Carver cv(mem);
+    D.XT = cv.take<double>((size_t)d * D.ldx);
+    D.prec = prec;
+    if (prec >= 0) {
+        const int64_t kp = mfma_kpad(prec, d);
+        const size_t eb = mfma_elem_bytes(prec);
+        D.xbar = cv.take<double>((size_t)d);
+        D.A0 = cv.take<char>((size_t)n * kp * eb);
+        D.A1 = mfma_terms(prec) == 2 ? (void *)cv.take<char>((size_t)n * kp * eb) : nullptr;
+        D.anorm = cv.take<float>((size_t)n);
+    } else {
+        D.xbar = nullptr;
+        D.A0 = D.A1 = nullptr;
+        D.anorm = nullptr;
+    }
+    hipError_t e = launch_transpose(D.X, n, d, D.ldx, D.XT, st);
+    if (e != hipSuccess || prec < 0) return e;
+    return launch_mfma_prep(prec, D.X, n, d, D.xbar, D.A0, D.A1, D.anorm, st);
+}
+
+int job_mfma_prec(int precision)
+{
+    switch (precision) {
+    case RRS_BF16_RECHECK: return MFMA_BF16;
+    case RRS_F32_RECHECK: return MFMA_F32;
+    case RRS_F32_PLAIN: return MFMA_F32_PLAIN;
+    default: return -1;
+    }
+}
+
+rrs_status job_validate(const JobSpec &s, int64_t n, int64_t d)
+{
+    if (s.nq < 0) return fail(RRS_E_INVAL, "number of queries must be >= 0 (got %lld)", (long long)s.nq);
+    if (n < 1) return fail(RRS_E_INVAL, "n must be >= 1 (got %lld)", (long long)n);
+    if (d < 2) return fail(RRS_E_INVAL, "d must be >= 2 (got %lld)", (long long)d);
+    if (s.K < 1) return fail(RRS_E_INVAL, "K must be >= 1 (got %lld)", (long long)s.K);
+    if (s.r < 1) return fail(RRS_E_INVAL, "n_refine must be >= 1 (got %d)", s.r);
+    if (!(s.alpha > 0.0 && s.alpha <= 1.0))
+        return fail(RRS_E_INVAL, "cap_shrink must be in (0, 1] (got %g)", s.alpha);
+    if (s.notion != NOTION_HALFSPACE && s.notion != NOTION_PROJECTION && s.notion != NOTION_APD)
+        return fail(RRS_E_INVAL, "unknown depth notion %d", s.notion);
+    if (s.precision != RRS_F64 && s.precision != RRS_F32_RECHECK &&
+        s.precision != RRS_BF16_RECHECK && s.precision != RRS_F32_PLAIN)
+        return fail(RRS_E_INVAL, "unknown precision %d", s.precision);
+    const bool mfma = s.precision != RRS_F64;
+    if (mfma && s.notion != NOTION_HALFSPACE)
+        return fail(RRS_E_INVAL, "precision %d is available for halfspace depth only",
+                    s.precision);
+    if (mfma && ((s.K + s.r - 1) / s.r >= 65536 || s.nq > 65535))
+        return fail(RRS_E_INVAL,
+                    "matrix-core precisions need ceil(K/n_refine) < 65536 directions and at "
+                    "most 65535 queries");
+    if (n > 0x7FFFFFFFLL || d > 0x7FFFFFFFLL)
+        return fail(RRS_E_INVAL, "n and d must fit in 31 bits");
+    if ((s.K + s.r - 1) / s.r > 0x7FFFFFFFLL)
+        return fail(RRS_E_INVAL, "ceil(K / n_refine) too large");
+    if (s.qoff < 0) return fail(RRS_E_INVAL, "query_offset must be >= 0");
+    return RRS_OK;
+}
+
+namespace {
+
+// Workspace pieces of a job with query batch qb (order = carve order).
+int job_sizes(const JobSpec &s, int64_t n, int64_t d, const Plan &p, int64_t qb, size_t *sz)
+{
+    const bool half = s.notion == NOTION_HALFSPACE;
+    const bool mfma = p.prec >= 0;
+    int k = 0;
+    sz[k++] = (size_t)qb * d * p.ldm * 8;                       // UT
+    sz[k++] = (size_t)qb * d * 8;                               // pole
+    sz[k++] = (size_t)qb * 8;                                   // best_d
+    sz[k++] = (size_t)qb * 8;                                   // best_c
+    sz[k++] = half ? (size_t)qb * p.ldm * 2 * 4 : 0;            // cnt
+    sz[k++] = half ? 0 : (size_t)qb * p.m * n * 8;              // T
+    sz[k++] = half ? 0 : (size_t)qb * p.ldm * 8;                // Dj
+    sz[k++] = 64;                                               // stats
+    sz[k++] = mfma ? (size_t)qb * p.ldb * p.kp * p.eb : 0;      // B0
+    sz[k++] = (mfma && p.terms == 2) ? (size_t)qb * p.ldb * p.kp * p.eb : 0;  // B1
+    sz[k++] = mfma ? (size_t)qb * p.ldb * 4 : 0;                // cmarg
+    sz[k++] = mfma ? (size_t)p.qcap * 8 : 0;                    // queue
+    sz[k++] = 64;                                               // qctl
+    return k;
+}
+
+uint64_t job_qcap(const Plan &p, int64_t n, int64_t qb)
+{
+    // recheck queue: 1% of the pairs of a launch, at least 1M entries
+    uint64_t qcap = (uint64_t)qb * (uint64_t)p.m * (uint64_t)n / 100;
+    if (qcap < (1u << 20)) qcap = 1u << 20;
+    if (qcap > 0xFFFFFFF0ull) qcap = 0xFFFFFFF0ull;
+    return qcap;
+}
+
+}  // namespace
+
+rrs_status job_plan(const JobSpec &s, int64_t n, int64_t d, size_t limit, Plan *out)
+{
+    Plan p;
+    p.prec = job_mfma_prec(s.precision);
+    p.m = (s.K + s.r - 1) / s.r;
+    p.ldm = (p.m + kProjJT - 1) / kProjJT * kProjJT;
+    p.ldb = (p.m + kMfmaCols - 1) / kMfmaCols * kMfmaCols;
+    if (p.prec >= 0) {
+        p.kp = mfma_kpad(p.prec, d);
+        p.eb = mfma_elem_bytes(p.prec);
+        p.terms = mfma_terms(p.prec);
+    }
+    // largest batch whose workspace fits the limit (the size grows with qb)
+    int64_t lo = 1, hi = s.nq < 65535 ? (s.nq > 0 ? s.nq : 1) : 65535;
+    size_t sz[16];
+    auto bytes = [&](int64_t qb) {
+        Plan t = p;
+        t.qcap = p.prec >= 0 ? job_qcap(p, n, qb) : 0;
+        const int k = job_sizes(s, n, d, t, qb, sz);
+        return carve_size(sz, k);
+    };
+    if (bytes(hi) > limit) {
+        while (lo < hi) {
+            const int64_t mid = lo + (hi - lo + 1) / 2;
+            if (bytes(mid) <= limit)
+                lo = mid;
+            else
+                hi = mid - 1;
+        }
+    } else {
+        lo = hi;
+    }
+    p.qb = lo;
+    p.qcap = p.prec >= 0 ? job_qcap(p, n, p.qb) : 0;
+    p.ws_bytes = bytes(p.qb);
+    *out = p;
+    return RRS_OK;
+}
+
+rrs_status enqueue_job(const JobSpec &s, const DataDev &D, const Plan &p, const JobIO &io,
+                       void *ws, hipStream_t st, Profiler *prof, uint32_t **stats_out)
+{
+    const int64_t n = D.n, d = D.d, nq = s.nq, m = p.m, ldm = p.ldm, ldb = p.ldb, qb = p.qb;
+    const int32_t r = s.r;
+    const bool half = s.notion == NOTION_HALFSPACE;
+    const bool mfma = p.prec >= 0;
+    const bool profiling = prof && prof->on;
+    if (mfma && D.prec != p.prec)
+        return fail(RRS_E_INTERNAL, "data set not prepared for matrix-core format %d", p.prec);
+    size_t sz[16];
+    job_sizes(s, n, d, p, qb, sz);
+    Carver cv(ws);
+    double *UT = cv.take<double>(sz[0] / 8);
+    double *pole = cv.take<double>(sz[1] / 8);
+    double *best_d = cv.take<double>(sz[2] / 8);
+    int64_t *best_c = cv.take<int64_t>(sz[3] / 8);
+    uint32_t *cnt = cv.take<uint32_t>(sz[4] / 4);
+    double *T = cv.take<double>(sz[5] / 8);
+    double *Dj = cv.take<double>(sz[6] / 8);
+    uint32_t *stats = cv.take<uint32_t>(16);
+    void *B0 = cv.take<char>(sz[8]);
+    void *B1 = cv.take<char>(sz[9]);
+    float *cmarg = cv.take<float>(sz[10] / 4);
+    uint64_t *queue = cv.take<uint64_t>(sz[11] / 8);
+    uint32_t *qctl = cv.take<uint32_t>(16);  // [0] queue length, [1] overflow flag
+    if (stats_out) *stats_out = stats;
+    if (profiling) RRS_HIP_TRY(launch_fill_u32(stats, 16, 0u, st));
+
+    // zero the direction padding once (the generator writes j < m only)
+    RRS_HIP_TRY(launch_fill_u32((uint32_t *)UT, qb * d * ldm * 2, 0u, st));
+    int dev = 0;
+    RRS_HIP_TRY(hipGetDevice(&dev));
+    const bool lds = !half && n <= select_lds_max_n(dev);
+    for (int64_t q0 = 0; q0 < nq; q0 += qb) {
+        const int64_t nb = (nq - q0 < qb) ? nq - q0 : qb;
+        const double *Zb = io.Z + q0 * d;
+        RRS_HIP_TRY(launch_init_state(nb, d, n, pole, best_d, best_c, st));
+        double phi = 1.0;
+        for (int32_t l = 1; l <= r; ++l) {
+            const double proj_units = (double)nb * (double)m * (double)n;
+            GenArgs ga{d, m, ldm, nb, l, phi, s.seed, (uint64_t)(s.qoff + q0), pole, UT};
+            {
+                ProfScope ps(prof, K_GEN, (double)nb * m * d, st);
+                RRS_HIP_TRY(launch_gen_dirs(ga, st));
+            }
+            ProjArgs pa{D.XT, D.ldx, n, d, Zb, UT, ldm, m, nb, cnt, T, nullptr};
+            if (half && mfma) {
+                RRS_HIP_TRY(launch_fill_u32(cnt, nb * ldm * 2, 0u, st));
+                RRS_HIP_TRY(launch_fill_u32(qctl, 16, 0u, st));
+                RRS_HIP_TRY(launch_mfma_dirs(p.prec, UT, d, m, ldm, ldb, nb, Zb, D.xbar, B0, B1,
+                                             cmarg, st));
+                MfmaArgs ma{p.prec, D.A0,   D.A1,   D.anorm, n,    d,    B0,
+                            B1,     cmarg,  m,      ldm,     ldb,  nb,   cnt,
+                            queue,  qctl,   p.qcap, qctl + 1, D.X, Zb,   UT,
+                            profiling ? (uint64_t *)(stats + 4) : nullptr};
+                {
+                    ProfScope ps(prof, K_MFMA, proj_units, st);
+                    RRS_HIP_TRY(launch_mfma_gemm(ma, st));
+                }
+                if (p.prec != MFMA_F32_PLAIN) {
+                    {
+                        ProfScope ps(prof, K_RECHECK, 0.0, st);
+                        RRS_HIP_TRY(launch_mfma_recheck(ma, st));
+                    }
+                    // queue overflow (never expected): recount in binary64
+                    pa.only_if = qctl + 1;
+                    RRS_HIP_TRY(launch_proj_f64(pa, true, st));
+                }
+            } else if (half) {
+                RRS_HIP_TRY(launch_fill_u32(cnt, nb * ldm * 2, 0u, st));
+                ProfScope ps(prof, K_PROJ, proj_units, st);
+                RRS_HIP_TRY(launch_proj_f64(pa, true, st));
+            } else {
+                {
+                    ProfScope ps(prof, K_PROJ, proj_units, st);
+                    RRS_HIP_TRY(launch_proj_f64(pa, false, st));
+                }
+                SelectArgs sa{T, n, m, ldm, nb, Dj, profiling ? stats : nullptr};
+                ProfScope ps(prof, K_SELECT, proj_units, st);
+                if (n <= select_reg_max_n())
+                    RRS_HIP_TRY(launch_select_reg(sa, s.notion, st));
+                else
+                    RRS_HIP_TRY(launch_select(sa, s.notion, lds, st));
+            }
+            ArgminArgs aa{m, ldm, d, nb, cnt, Dj, UT, pole, best_d, best_c,
+                          io.trace ? io.trace + q0 * r * 3 : nullptr, l, r};
+            {
+                ProfScope ps(prof, K_ARGMIN, (double)nb * m, st);
+                RRS_HIP_TRY(launch_argmin(aa, half, st));
+            }
+            phi = phi * s.alpha;
+        }
+        RRS_HIP_TRY(launch_finalize(nb, d, n, half, pole, best_d, best_c, io.depth + q0,
+                                    io.count ? io.count + q0 : nullptr,
+                                    io.poles ? io.poles + q0 * d : nullptr, st));
+    }
+    return RRS_OK;
+}
+
+}  // namespace rrs

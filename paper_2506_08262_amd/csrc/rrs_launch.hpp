@@ -31,11 +31,14 @@ struct ProjArgs {
 };
 
 // Halfspace counts on matrix cores (rrs_mfma.hip).
+enum { MFMA_BF16 = 0, MFMA_F32 = 1, MFMA_F32_PLAIN = 2 };
+
 struct MfmaArgs {
-    const __bf16 *Ahi, *Alo;   // [n][kp] centred data, two bf16 terms
+    int prec;                  // MFMA_*
+    const void *A0, *A1;       // [n][kp] centred data: bf16 hi/lo, or binary32 in A0
     const float *anorm;        // [n] norm bound of the centred points
     int64_t n, d;
-    const __bf16 *Bhi, *Blo;   // [qb][ldb][kp] split directions + centring
+    const void *B0, *B1;       // [qb][ldb][kp] directions + centring, same format
     const float *cmarg;        // [qb][ldb] direction part of the margin
     int64_t m, ldm, ldb, qb;
     uint32_t *cnt;             // [qb][ldm][2]
@@ -46,6 +49,7 @@ struct MfmaArgs {
     const double *X;           // [n][d] binary64 data (recheck)
     const double *Z;           // [qb][d] queries of the batch
     const double *UT;          // [qb][d][ldm] binary64 directions
+    uint64_t *tally;           // optional: running total of rechecked pairs
 };
 
 struct SelectArgs {
@@ -77,14 +81,17 @@ hipError_t launch_select(const SelectArgs &a, int notion, bool lds, hipStream_t 
 int64_t select_reg_max_n();
 hipError_t launch_select_reg(const SelectArgs &a, int notion, hipStream_t st);
 hipError_t launch_argmin(const ArgminArgs &a, bool half, hipStream_t st);
-int64_t mfma_kpad(int64_t d);
-void mfma_margins(int64_t d, int64_t kp, double *kappa, double *canon);
-hipError_t launch_mfma_prep(const double *X, int64_t n, int64_t d, double *xbar, __bf16 *Ahi,
-                            __bf16 *Alo, float *anorm, hipStream_t st);
-hipError_t launch_mfma_dirs(const double *UT, int64_t d, int64_t m, int64_t ldm, int64_t ldb,
-                            int64_t qb, const double *Zb, const double *xbar, __bf16 *Bhi,
-                            __bf16 *Blo, float *cmarg, hipStream_t st);
-hipError_t launch_mfma_count(const MfmaArgs &a, hipStream_t st);
+int64_t mfma_kpad(int prec, int64_t d);
+size_t mfma_elem_bytes(int prec);
+int mfma_terms(int prec);
+void mfma_margins(int prec, int64_t d, int64_t kp, double *kappa, double *canon);
+hipError_t launch_mfma_prep(int prec, const double *X, int64_t n, int64_t d, double *xbar,
+                            void *A0, void *A1, float *anorm, hipStream_t st);
+hipError_t launch_mfma_dirs(int prec, const double *UT, int64_t d, int64_t m, int64_t ldm,
+                            int64_t ldb, int64_t qb, const double *Zb, const double *xbar,
+                            void *B0, void *B1, float *cmarg, hipStream_t st);
+hipError_t launch_mfma_gemm(const MfmaArgs &a, hipStream_t st);
+hipError_t launch_mfma_recheck(const MfmaArgs &a, hipStream_t st);
 constexpr int kMfmaCols = 64;  // directions per matrix-core workgroup
 hipError_t launch_init_state(int64_t qb, int64_t d, int64_t n, double *pole, double *best_d,
                              int64_t *best_c, hipStream_t st);

@@ -1,19 +1,20 @@
 // rrs_mfma.hip -- halfspace depth with the projection on CDNA4 matrix cores
-// (BF16 inputs, FP32 accumulation) and an exact FP64 recheck.
+// and, for the exact forms, an FP64 recheck of the uncertain signs.
 //
-// Step a2 + a3 (+ a4) for halfspace depth, precision form RRS_BF16_RECHECK:
-//   * the data is centred by its mean xbar (binary64), a_i = x_i - xbar, and
-//     split into two bfloat16 terms a = a_hi + a_lo (+ remainder);
-//   * each direction u_j is split the same way; the query's centring term
-//     c_j = (z - xbar).u_j (binary64) is folded into two extra K columns
-//     (A: 1, 1; B: -c_hi, -c_lo), so one GEMM row-by-column product is
-//     t^_ij ~ a_i.u_j - c_j = (x_i - z).u_j;
-//   * t^ = A_hi B_hi + A_hi B_lo + A_lo B_hi on v_mfma_f32_32x32x16_bf16;
-//   * the epilogue decides the sign of the recipe's binary64 projection when
-//     |t^| exceeds a rigorous margin M_ij = kappa (|a_i| + |c_j|) + e_canon,
-//     and queues (query, point, direction) otherwise; the recheck kernel
-//     recomputes those projections with the binary64 recipe.
-// Counts are integers, so the result is identical to the binary64 form.
+// Step a2 + a3 (+ a4) for halfspace depth.  Every form centres the data by
+// its mean xbar (binary64), a_i = x_i - xbar, and folds the query's centring
+// term c_j = (z - xbar).u_j (binary64) into extra K columns (A: 1; B: -c), so
+// that one GEMM row-by-column product is t^_ij ~ a_i.u_j - c_j = (x_i - z).u_j.
+//   RRS_BF16_RECHECK: a and u are split into two bfloat16 terms,
+//     t^ = A_hi B_hi + A_hi B_lo + A_lo B_hi on v_mfma_f32_32x32x16_bf16;
+//   RRS_F32_RECHECK / RRS_F32_PLAIN: a, u and c rounded to binary32,
+//     t^ = A B on v_mfma_f32_32x32x2_f32.
+// The recheck forms take the sign of the recipe's binary64 projection from t^
+// when |t^| exceeds a rigorous margin M_ij = kappa (|a_i| + |c_j|) + e_canon
+// and queue (query, point, direction) otherwise; the recheck kernel
+// recomputes those projections with the binary64 recipe, so the counts are
+// identical to the binary64 form.  The plain form takes every sign from t^
+// (t^ == 0 counts on both sides) and is approximate.
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdint.h>
@@ -25,6 +26,7 @@ namespace rrs {
 namespace {
 
 typedef __attribute__((ext_vector_type(8))) __bf16 bf16x8;
+typedef __attribute__((ext_vector_type(4))) float f32x4;
 typedef __attribute__((ext_vector_type(16))) float f32x16;
 
 constexpr int kNJ = 2;            // 32-direction tiles per wave
@@ -36,8 +38,8 @@ __device__ __forceinline__ __bf16 to_bf16(double v) { return (__bf16)(float)v; }
 __device__ __forceinline__ double from_bf16(__bf16 v) { return (double)(float)v; }
 
 // ---------------------------------------------------------------------------
-// Data preparation (once per call): column means, centred split operands and
-// the norm of every centred point.
+// Data preparation (once per call): column means, centred operands and the
+// norm of every centred point.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_col_mean(const double *__restrict__ X, int64_t n,
                                                   int64_t d, double *__restrict__ xbar)
@@ -56,58 +58,67 @@ __global__ __launch_bounds__(256) void k_col_mean(const double *__restrict__ X, 
     if (threadIdx.x == 0) xbar[c] = red[0] / (double)n;
 }
 
-__global__ __launch_bounds__(256) void k_split_data(const double *__restrict__ X, int64_t n,
-                                                    int64_t d, int64_t kp,
-                                                    const double *__restrict__ xbar,
-                                                    __bf16 *__restrict__ Ahi,
-                                                    __bf16 *__restrict__ Alo,
-                                                    float *__restrict__ anorm)
+// A0/A1 [n][kp]: bf16 hi/lo terms (BF16) or binary32 values in A0 (F32).
+template <int PREC>
+__global__ __launch_bounds__(256) void k_prep_data(const double *__restrict__ X, int64_t n,
+                                                   int64_t d, int64_t kp,
+                                                   const double *__restrict__ xbar,
+                                                   void *__restrict__ A0, void *__restrict__ A1,
+                                                   float *__restrict__ anorm)
 {
     const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (i >= n) return;
+    // column d (and d + 1 for BF16) multiplies the folded centring term
+    const int64_t nfold = PREC == MFMA_BF16 ? 2 : 1;
     double ss = 0.0;
     for (int64_t c = 0; c < kp; ++c) {
-        __bf16 h, l;
+        double a = 0.0;
         if (c < d) {
-            const double a = X[i * d + c] - xbar[c];
-            h = to_bf16(a);
-            l = to_bf16(a - from_bf16(h));
+            a = X[i * d + c] - xbar[c];
             ss = fma(a, a, ss);
-        } else if (c < d + 2) {
-            h = (__bf16)1.0f;  // multiplies the folded centring terms
-            l = (__bf16)0.0f;
-        } else {
-            h = (__bf16)0.0f;
-            l = (__bf16)0.0f;
+        } else if (c < d + nfold) {
+            a = 1.0;
         }
-        Ahi[i * kp + c] = h;
-        Alo[i * kp + c] = l;
+        if (PREC == MFMA_BF16) {
+            const __bf16 h = to_bf16(a);
+            ((__bf16 *)A0)[i * kp + c] = h;
+            ((__bf16 *)A1)[i * kp + c] = c < d ? to_bf16(a - from_bf16(h)) : (__bf16)0.0f;
+        } else {
+            ((float *)A0)[i * kp + c] = (float)a;
+        }
     }
     // upper bound of the norm, rounded up to binary32
     const float nf = (float)sqrt(ss);
     anorm[i] = nf * (1.0f + 1e-6f);
 }
 
-// Per refinement: split the directions (binary64, [q][d][ldm] in UT) and fold
-// the centring term; cmarg[q][j] = kappa |c_j| + slack (binary32, rounded up).
-__global__ __launch_bounds__(64) void k_split_dirs(const double *__restrict__ UT, int64_t d,
-                                                   int64_t m, int64_t ldm, int64_t ldb,
-                                                   int64_t kp, const double *__restrict__ Zb,
-                                                   const double *__restrict__ xbar,
-                                                   double kappa, double canon,
-                                                   __bf16 *__restrict__ Bhi,
-                                                   __bf16 *__restrict__ Blo,
-                                                   float *__restrict__ cmarg)
+// Per refinement: the directions (binary64, [q][d][ldm] in UT) in the GEMM's
+// operand format with the centring term folded in; cmarg[q][j] = kappa |c_j|
+// + slack (binary32, rounded up).
+template <int PREC>
+__global__ __launch_bounds__(64) void k_prep_dirs(const double *__restrict__ UT, int64_t d,
+                                                  int64_t m, int64_t ldm, int64_t ldb,
+                                                  int64_t kp, const double *__restrict__ Zb,
+                                                  const double *__restrict__ xbar, double kappa,
+                                                  double canon, void *__restrict__ B0,
+                                                  void *__restrict__ B1,
+                                                  float *__restrict__ cmarg)
 {
     const int64_t j = (int64_t)blockIdx.x * 64 + threadIdx.x;
     const int64_t qi = blockIdx.y;
     if (j >= ldb) return;
-    __bf16 *bh = Bhi + (qi * ldb + j) * kp;
-    __bf16 *bl = Blo + (qi * ldb + j) * kp;
+    const int64_t off = (qi * ldb + j) * kp;
+    __bf16 *bh = (__bf16 *)B0 + off;
+    __bf16 *bl = (__bf16 *)B1 + off;
+    float *bf = (float *)B0 + off;
     if (j >= m) {
         for (int64_t c = 0; c < kp; ++c) {
-            bh[c] = (__bf16)0.0f;
-            bl[c] = (__bf16)0.0f;
+            if (PREC == MFMA_BF16) {
+                bh[c] = (__bf16)0.0f;
+                bl[c] = (__bf16)0.0f;
+            } else {
+                bf[c] = 0.0f;
+            }
         }
         cmarg[qi * ldb + j] = 0.0f;
         return;
@@ -120,18 +131,33 @@ __global__ __launch_bounds__(64) void k_split_dirs(const double *__restrict__ UT
         const double b = z[c] - xbar[c];
         cj = fma(b, uc, cj);
         bn = fma(b, b, bn);
-        const __bf16 h = to_bf16(uc);
-        bh[c] = h;
-        bl[c] = to_bf16(uc - from_bf16(h));
+        if (PREC == MFMA_BF16) {
+            const __bf16 h = to_bf16(uc);
+            bh[c] = h;
+            bl[c] = to_bf16(uc - from_bf16(h));
+        } else {
+            bf[c] = (float)uc;
+        }
     }
-    const __bf16 ch = to_bf16(-cj);
-    bh[d] = ch;
-    bh[d + 1] = to_bf16(-cj - from_bf16(ch));
-    bl[d] = (__bf16)0.0f;
-    bl[d + 1] = (__bf16)0.0f;
-    for (int64_t c = d + 2; c < kp; ++c) {
-        bh[c] = (__bf16)0.0f;
-        bl[c] = (__bf16)0.0f;
+    int64_t c0;
+    if (PREC == MFMA_BF16) {
+        const __bf16 ch = to_bf16(-cj);
+        bh[d] = ch;
+        bh[d + 1] = to_bf16(-cj - from_bf16(ch));
+        bl[d] = (__bf16)0.0f;
+        bl[d + 1] = (__bf16)0.0f;
+        c0 = d + 2;
+    } else {
+        bf[d] = (float)(-cj);
+        c0 = d + 1;
+    }
+    for (int64_t c = c0; c < kp; ++c) {
+        if (PREC == MFMA_BF16) {
+            bh[c] = (__bf16)0.0f;
+            bl[c] = (__bf16)0.0f;
+        } else {
+            bf[c] = 0.0f;
+        }
     }
     // margin part that depends on the direction only: kappa |c_j| plus the
     // binary64 recipe's own error through |z - xbar|; the data part
@@ -142,15 +168,22 @@ __global__ __launch_bounds__(64) void k_split_dirs(const double *__restrict__ UT
 
 // ---------------------------------------------------------------------------
 // GEMM + sign epilogue.  Workgroup: 4 waves x 32 points, all sharing
-// kNJ x 32 directions of one query.  Lane layout of v_mfma_f32_32x32x16_bf16:
-// A row i = lane % 32 holds K elements 8 (lane / 32) .. +7 of the 16-step;
-// B column j = lane % 32 likewise; accumulator r holds row
-// (r / 4) 8 + (lane / 32) 4 + r % 4 of column lane % 32.
+// kNJ x 32 directions of one query.  Lane layouts (lr = lane % 32,
+// lh = lane / 32):
+//   v_mfma_f32_32x32x16_bf16: A row lr holds K elements 8 lh .. 8 lh + 7 of
+//     the 16-step, B column lr likewise;
+//   v_mfma_f32_32x32x2_f32: A row lr holds K element lh of the 2-step, B
+//     column lr likewise.  Each lane loads 4 consecutive floats of its row
+//     (K elements 8 g + 4 lh .. + 3 of group g) and feeds them to 4 MFMAs, so
+//     the 4 steps of a group cover its 8 K elements once (A and B use the same
+//     assignment, so the sum is the full dot product);
+//   both: accumulator r holds row (r / 4) 8 + 4 lh + r % 4 of column lr.
 // ---------------------------------------------------------------------------
+template <int PREC>
 __global__ __launch_bounds__(256) void k_gemm_sign(
-    const __bf16 *__restrict__ Ahi, const __bf16 *__restrict__ Alo,
+    const void *__restrict__ A0, const void *__restrict__ A1,
     const float *__restrict__ anorm, int64_t n, int64_t kp,
-    const __bf16 *__restrict__ Bhi, const __bf16 *__restrict__ Blo,
+    const void *__restrict__ B0, const void *__restrict__ B1,
     const float *__restrict__ cmarg, int64_t m, int64_t ldm, int64_t ldb, float kappa_a,
     uint32_t *__restrict__ cnt, uint64_t *__restrict__ queue, uint32_t *__restrict__ qcount,
     uint64_t qcap)
@@ -169,46 +202,74 @@ __global__ __launch_bounds__(256) void k_gemm_sign(
 
     int64_t arow = row0 + lr;
     if (arow > n - 1) arow = n - 1;  // clamp; results of rows >= n are ignored
-    const __bf16 *ah = Ahi + arow * kp + 8 * lh;
-    const __bf16 *al = Alo + arow * kp + 8 * lh;
-    const __bf16 *bh[kNJ], *bl[kNJ];
-#pragma unroll
-    for (int t = 0; t < kNJ; ++t) {
-        const int64_t col = qi * ldb + j0 + 32 * t + lr;  // < qb * ldb: ldb covers the grid
-        bh[t] = Bhi + col * kp + 8 * lh;
-        bl[t] = Blo + col * kp + 8 * lh;
-    }
-    for (int64_t k = 0; k < kp; k += 16) {
-        const bf16x8 a_h = *(const bf16x8 *)(ah + k);
-        const bf16x8 a_l = *(const bf16x8 *)(al + k);
+    if (PREC == MFMA_BF16) {
+        const __bf16 *ah = (const __bf16 *)A0 + arow * kp + 8 * lh;
+        const __bf16 *al = (const __bf16 *)A1 + arow * kp + 8 * lh;
+        const __bf16 *bh[kNJ], *bl[kNJ];
 #pragma unroll
         for (int t = 0; t < kNJ; ++t) {
-            const bf16x8 b_h = *(const bf16x8 *)(bh[t] + k);
-            const bf16x8 b_l = *(const bf16x8 *)(bl[t] + k);
-            acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a_h, b_h, acc[t], 0, 0, 0);
-            acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a_h, b_l, acc[t], 0, 0, 0);
-            acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a_l, b_h, acc[t], 0, 0, 0);
+            const int64_t col = qi * ldb + j0 + 32 * t + lr;  // < qb * ldb: ldb covers the grid
+            bh[t] = (const __bf16 *)B0 + col * kp + 8 * lh;
+            bl[t] = (const __bf16 *)B1 + col * kp + 8 * lh;
+        }
+        for (int64_t k = 0; k < kp; k += 16) {
+            const bf16x8 a_h = *(const bf16x8 *)(ah + k);
+            const bf16x8 a_l = *(const bf16x8 *)(al + k);
+#pragma unroll
+            for (int t = 0; t < kNJ; ++t) {
+                const bf16x8 b_h = *(const bf16x8 *)(bh[t] + k);
+                const bf16x8 b_l = *(const bf16x8 *)(bl[t] + k);
+                acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a_h, b_h, acc[t], 0, 0, 0);
+                acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a_h, b_l, acc[t], 0, 0, 0);
+                acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a_l, b_h, acc[t], 0, 0, 0);
+            }
+        }
+    } else {
+        const float *af = (const float *)A0 + arow * kp + 4 * lh;
+        const float *bf[kNJ];
+#pragma unroll
+        for (int t = 0; t < kNJ; ++t) {
+            const int64_t col = qi * ldb + j0 + 32 * t + lr;
+            bf[t] = (const float *)B0 + col * kp + 4 * lh;
+        }
+        for (int64_t k = 0; k < kp; k += 8) {
+            const f32x4 a = *(const f32x4 *)(af + k);
+#pragma unroll
+            for (int t = 0; t < kNJ; ++t) {
+                const f32x4 b = *(const f32x4 *)(bf[t] + k);
+                acc[t] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[0], b[0], acc[t], 0, 0, 0);
+                acc[t] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[1], b[1], acc[t], 0, 0, 0);
+                acc[t] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[2], b[2], acc[t], 0, 0, 0);
+                acc[t] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[3], b[3], acc[t], 0, 0, 0);
+            }
         }
     }
 
     // epilogue: per lane, one column per tile, 16 rows
+    constexpr bool kPlain = PREC == MFMA_F32_PLAIN;
     float an[16];
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
         const int64_t i = row0 + (r >> 2) * 8 + lh * 4 + (r & 3);
-        an[r] = i < n ? anorm[i] : 0.0f;
+        an[r] = (!kPlain && i < n) ? anorm[i] : 0.0f;
     }
     __shared__ uint32_t red[kWaves][32 * kNJ][2];
 #pragma unroll
     for (int t = 0; t < kNJ; ++t) {
         const int64_t j = j0 + 32 * t + lr;
-        const float cm = j < m ? cmarg[qi * ldb + j] : 0.0f;
+        const float cm = (!kPlain && j < m) ? cmarg[qi * ldb + j] : 0.0f;
         uint32_t pos = 0, neg = 0;
 #pragma unroll
         for (int r = 0; r < 16; ++r) {
             const int64_t i = row0 + (r >> 2) * 8 + lh * 4 + (r & 3);
             const bool live = i < n && j < m;
             const float v = acc[t][r];
+            if (kPlain) {
+                // sign of t^ itself; zero counts on both sides
+                pos += (live && v >= 0.0f) ? 1u : 0u;
+                neg += (live && v <= 0.0f) ? 1u : 0u;
+                continue;
+            }
             const float marg = fmaf(kappa_a, an[r], cm);
             const bool sp = live && v > marg;
             const bool sn = live && v < -marg;
@@ -246,9 +307,11 @@ __global__ __launch_bounds__(256) void k_recheck(const uint64_t *__restrict__ qu
                                                  uint64_t qcap, const double *__restrict__ X,
                                                  int64_t d, const double *__restrict__ Zb,
                                                  const double *__restrict__ UT, int64_t ldm,
-                                                 uint32_t *__restrict__ cnt)
+                                                 uint32_t *__restrict__ cnt,
+                                                 unsigned long long *__restrict__ tally)
 {
     const uint64_t total = *qcount < qcap ? *qcount : qcap;
+    if (tally && blockIdx.x == 0 && threadIdx.x == 0) atomicAdd(tally, (unsigned long long)total);
     for (uint64_t e = (uint64_t)blockIdx.x * 256 + threadIdx.x; e < total;
          e += (uint64_t)gridDim.x * 256) {
         const uint64_t w = queue[e];
@@ -280,59 +343,106 @@ __global__ __launch_bounds__(256) void k_overflow_reset(const uint32_t *__restri
 
 }  // namespace
 
-// kappa for the three-term bf16 product with binary32 accumulation of K
-// terms (see the design doc for the derivation); canon = binary64 recipe slack.
-void mfma_margins(int64_t d, int64_t kp, double *kappa, double *canon)
+// Error bounds of the matrix-core forms (kappa multiplies |a_i| + |c_j|).
+//
+// BF16: split |a - a_hi| <= 2^-8 |a| and the remainder |a - a_hi - a_lo| <=
+// 2^-17 |a| (a_lo lies one binade below 2^-8 |a|), so the dropped a_lo b_lo
+// and the two remainder products miss at most (2^-16 + 2 * 2^-17)(1 + 2^-8)
+// |a||b| <= 4.5 * 2^-17 |a||b|; summed over the coordinates this is bounded
+// by |a|_2 |u|_2 (Cauchy-Schwarz).  The bf16 products are exact in binary32
+// and each of the 3 kp + 16 additions adds at most 2^-24 of the running sum
+// of magnitudes (doubled for slack).
+//
+// F32: a, u and c are each rounded once to binary32 (relative 2^-24), each
+// product is rounded at most once and each of the kp additions adds at most
+// 2^-24 of the sum of magnitudes: (kp + 4) 2^-24, doubled for slack.
+//
+// canon bounds the binary64 recipe's own distance from the exact product.
+void mfma_margins(int prec, int64_t d, int64_t kp, double *kappa, double *canon)
 {
-    const double split = 3.0 * ldexp(1.0, -17) * 1.5;          // dropped lo*lo + remainders
-    const double accum = 2.0 * (double)(3 * kp + 16) * ldexp(1.0, -24);
-    *kappa = split + accum;
-    *canon = 2.0 * (double)(d + 2) * ldexp(1.0, -53);
+    if (prec == MFMA_BF16) {
+        const double split = 3.0 * ldexp(1.0, -17) * 1.5;
+        const double accum = 2.0 * (double)(3 * kp + 16) * ldexp(1.0, -24);
+        *kappa = split + accum;
+    } else if (prec == MFMA_F32) {
+        *kappa = 2.0 * (double)(kp + 4) * ldexp(1.0, -24);
+    } else {
+        *kappa = 0.0;
+    }
+    *canon = prec == MFMA_F32_PLAIN ? 0.0 : 2.0 * (double)(d + 2) * ldexp(1.0, -53);
 }
 
-int64_t mfma_kpad(int64_t d) { return (d + 2 + 15) / 16 * 16; }
+int64_t mfma_kpad(int prec, int64_t d)
+{
+    return prec == MFMA_BF16 ? (d + 2 + 15) / 16 * 16 : (d + 1 + 7) / 8 * 8;
+}
 
-hipError_t launch_mfma_prep(const double *X, int64_t n, int64_t d, double *xbar, __bf16 *Ahi,
-                            __bf16 *Alo, float *anorm, hipStream_t st)
+size_t mfma_elem_bytes(int prec) { return prec == MFMA_BF16 ? 2 : 4; }
+int mfma_terms(int prec) { return prec == MFMA_BF16 ? 2 : 1; }
+
+hipError_t launch_mfma_prep(int prec, const double *X, int64_t n, int64_t d, double *xbar,
+                            void *A0, void *A1, float *anorm, hipStream_t st)
 {
     hipLaunchKernelGGL(k_col_mean, dim3((unsigned)d), dim3(256), 0, st, X, n, d, xbar);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_split_data, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, X, n,
-                       d, mfma_kpad(d), xbar, Ahi, Alo, anorm);
+    const dim3 grid((unsigned)((n + 255) / 256));
+    const int64_t kp = mfma_kpad(prec, d);
+    if (prec == MFMA_BF16)
+        hipLaunchKernelGGL(k_prep_data<MFMA_BF16>, grid, dim3(256), 0, st, X, n, d, kp, xbar,
+                           A0, A1, anorm);
+    else
+        hipLaunchKernelGGL(k_prep_data<MFMA_F32>, grid, dim3(256), 0, st, X, n, d, kp, xbar, A0,
+                           A1, anorm);
     return hipGetLastError();
 }
 
-hipError_t launch_mfma_dirs(const double *UT, int64_t d, int64_t m, int64_t ldm, int64_t ldb,
-                            int64_t qb, const double *Zb, const double *xbar, __bf16 *Bhi,
-                            __bf16 *Blo, float *cmarg, hipStream_t st)
+hipError_t launch_mfma_dirs(int prec, const double *UT, int64_t d, int64_t m, int64_t ldm,
+                            int64_t ldb, int64_t qb, const double *Zb, const double *xbar,
+                            void *B0, void *B1, float *cmarg, hipStream_t st)
 {
     double kappa, canon;
-    const int64_t kp = mfma_kpad(d);
-    mfma_margins(d, kp, &kappa, &canon);
+    const int64_t kp = mfma_kpad(prec, d);
+    mfma_margins(prec, d, kp, &kappa, &canon);
     dim3 grid((unsigned)((ldb + 63) / 64), (unsigned)qb);
-    hipLaunchKernelGGL(k_split_dirs, grid, dim3(64), 0, st, UT, d, m, ldm, ldb, kp, Zb, xbar,
-                       kappa, canon, Bhi, Blo, cmarg);
+    if (prec == MFMA_BF16)
+        hipLaunchKernelGGL(k_prep_dirs<MFMA_BF16>, grid, dim3(64), 0, st, UT, d, m, ldm, ldb, kp,
+                           Zb, xbar, kappa, canon, B0, B1, cmarg);
+    else
+        hipLaunchKernelGGL(k_prep_dirs<MFMA_F32>, grid, dim3(64), 0, st, UT, d, m, ldm, ldb, kp,
+                           Zb, xbar, kappa, canon, B0, B1, cmarg);
     return hipGetLastError();
 }
 
-hipError_t launch_mfma_count(const MfmaArgs &a, hipStream_t st)
+hipError_t launch_mfma_gemm(const MfmaArgs &a, hipStream_t st)
 {
     double kappa, canon;
-    const int64_t kp = mfma_kpad(a.d);
-    mfma_margins(a.d, kp, &kappa, &canon);
+    const int64_t kp = mfma_kpad(a.prec, a.d);
+    mfma_margins(a.prec, a.d, kp, &kappa, &canon);
     const float kappa_a = (float)((kappa + canon) * 1.000001);
     dim3 grid((unsigned)((a.m + 32 * kNJ - 1) / (32 * kNJ)), (unsigned)a.qb,
               (unsigned)((a.n + kRowsPerWave * kWaves - 1) / (kRowsPerWave * kWaves)));
     if (a.ldb < (int64_t)grid.x * 32 * kNJ) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_gemm_sign, grid, dim3(256), 0, st, a.Ahi, a.Alo, a.anorm, a.n, kp,
-                       a.Bhi, a.Blo, a.cmarg, a.m, a.ldm, a.ldb, kappa_a, a.cnt, a.queue,
-                       a.qcount, a.qcap);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
+#define RRS_GEMM(P)                                                                           \
+    hipLaunchKernelGGL(k_gemm_sign<P>, grid, dim3(256), 0, st, a.A0, a.A1, a.anorm, a.n, kp,  \
+                       a.B0, a.B1, a.cmarg, a.m, a.ldm, a.ldb, kappa_a, a.cnt, a.queue,       \
+                       a.qcount, a.qcap)
+    if (a.prec == MFMA_BF16)
+        RRS_GEMM(MFMA_BF16);
+    else if (a.prec == MFMA_F32)
+        RRS_GEMM(MFMA_F32);
+    else
+        RRS_GEMM(MFMA_F32_PLAIN);
+#undef RRS_GEMM
+    return hipGetLastError();
+}
+
+hipError_t launch_mfma_recheck(const MfmaArgs &a, hipStream_t st)
+{
+    if (a.prec == MFMA_F32_PLAIN) return hipSuccess;
     hipLaunchKernelGGL(k_recheck, dim3(1024), dim3(256), 0, st, a.queue, a.qcount, a.qcap, a.X,
-                       a.d, a.Z, a.UT, a.ldm, a.cnt);
-    e = hipGetLastError();
+                       a.d, a.Z, a.UT, a.ldm, a.cnt, (unsigned long long *)a.tally);
+    hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     const int64_t total = a.qb * a.ldm * 2;
     hipLaunchKernelGGL(k_overflow_reset, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st,

@@ -16,15 +16,20 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "librrs.so")
 
-RRS_OK, RRS_E_INVAL, RRS_E_NOMEM, RRS_E_DEVICE, RRS_E_INTERNAL = 0, 1, 2, 3, 6
-RRS_F64, RRS_BF16_RECHECK = 0, 2
-PRECISIONS = {"f64": RRS_F64, "bf16": RRS_BF16_RECHECK}
+RRS_OK, RRS_E_INVAL, RRS_E_NOMEM, RRS_E_DEVICE = 0, 1, 2, 3
+RRS_E_BUSY, RRS_E_CANCELLED, RRS_E_INTERNAL = 4, 5, 6
+RRS_F64, RRS_F32_RECHECK, RRS_BF16_RECHECK, RRS_F32_PLAIN = 0, 1, 2, 3
+PRECISIONS = {"f64": RRS_F64, "f32": RRS_F32_RECHECK, "bf16": RRS_BF16_RECHECK,
+              "f32_plain": RRS_F32_PLAIN}
 STATUS_NAMES = {0: "RRS_OK", 1: "RRS_E_INVAL", 2: "RRS_E_NOMEM", 3: "RRS_E_DEVICE",
-                6: "RRS_E_INTERNAL"}
+                4: "RRS_E_BUSY", 5: "RRS_E_CANCELLED", 6: "RRS_E_INTERNAL"}
+NOTIONS = {"halfspace": 0, "projection": 1, "apd": 2}
 
 EXPORTED = ["rrs_depth_halfspace", "rrs_depth_projection", "rrs_depth_apd",
             "rrs_last_error", "rrs_release_workspace", "rrs_version", "rrs_debug_directions",
-            "rrs_profile_enable", "rrs_profile_read", "rrs_profile_counter"]
+            "rrs_profile_enable", "rrs_profile_read", "rrs_profile_counter",
+            "rrs_ctx_create", "rrs_ctx_destroy", "rrs_dataset_put", "rrs_dataset_release",
+            "rrs_submit", "rrs_wait", "rrs_ctx_get_stats"]
 
 
 class RRSError(RuntimeError):
@@ -48,6 +53,32 @@ class rrs_kernel_stat(ctypes.Structure):
                 ("launches", ctypes.c_int64),
                 ("total_ms", ctypes.c_double),
                 ("work_units", ctypes.c_double)]
+
+
+class rrs_ctx_config(ctypes.Structure):
+    _fields_ = [("device", ctypes.c_int32),
+                ("slots", ctypes.c_int32),
+                ("hbm_budget", ctypes.c_size_t),
+                ("request_ws_limit", ctypes.c_size_t)]
+
+
+class rrs_request_info(ctypes.Structure):
+    _fields_ = [("submit_s", ctypes.c_double),
+                ("admit_s", ctypes.c_double),
+                ("done_s", ctypes.c_double),
+                ("projections", ctypes.c_int64),
+                ("bytes", ctypes.c_size_t)]
+
+
+class rrs_ctx_stats(ctypes.Structure):
+    _fields_ = [("pending", ctypes.c_int64),
+                ("running", ctypes.c_int64),
+                ("completed", ctypes.c_int64),
+                ("failed", ctypes.c_int64),
+                ("datasets", ctypes.c_int64),
+                ("bytes_in_use", ctypes.c_size_t),
+                ("bytes_peak", ctypes.c_size_t),
+                ("budget", ctypes.c_size_t)]
 
 
 _lib = None
@@ -90,6 +121,21 @@ def load(path: str = LIB_PATH):
     L.rrs_profile_read.restype = i32
     L.rrs_profile_counter.argtypes = [ctypes.c_char_p, ctypes.POINTER(ctypes.c_double)]
     L.rrs_profile_counter.restype = i32
+    L.rrs_ctx_create.argtypes = [ctypes.POINTER(rrs_ctx_config), ctypes.POINTER(p)]
+    L.rrs_ctx_create.restype = ctypes.c_int
+    L.rrs_ctx_destroy.argtypes = [p]
+    L.rrs_ctx_destroy.restype = ctypes.c_int
+    L.rrs_dataset_put.argtypes = [p, p, i64, i64, ctypes.POINTER(p)]
+    L.rrs_dataset_put.restype = ctypes.c_int
+    L.rrs_dataset_release.argtypes = [p, p]
+    L.rrs_dataset_release.restype = ctypes.c_int
+    L.rrs_submit.argtypes = [p, p, i32, p, i64, i64, i32, dbl, u64, ctypes.POINTER(rrs_opts),
+                             ctypes.POINTER(p)]
+    L.rrs_submit.restype = ctypes.c_int
+    L.rrs_wait.argtypes = [p, dbl, p, p, ctypes.POINTER(rrs_request_info)]
+    L.rrs_wait.restype = ctypes.c_int
+    L.rrs_ctx_get_stats.argtypes = [p, ctypes.POINTER(rrs_ctx_stats)]
+    L.rrs_ctx_get_stats.restype = ctypes.c_int
     _lib = L
     return L
 
@@ -252,3 +298,94 @@ def rrs_profile_counter(name: str):
     v = ctypes.c_double()
     rc = load().rrs_profile_counter(name.encode(), ctypes.byref(v))
     return float(v.value) if rc == 0 else None
+
+
+# --------------------------------------------------------------------------
+# Serving: resident data sets and continuously batched requests
+# --------------------------------------------------------------------------
+class Dataset:
+    """A data set resident in a Context (rrs_dataset_put)."""
+
+    def __init__(self, ctx, handle, n, d):
+        self.ctx, self.handle, self.n, self.d = ctx, handle, n, d
+
+    def release(self):
+        if self.handle is not None:
+            _check(load().rrs_dataset_release(self.ctx.handle, self.handle))
+            self.handle = None
+
+
+class Request:
+    """A submitted depth request (rrs_submit); wait() returns its result."""
+
+    def __init__(self, handle, nq, notion):
+        self.handle, self.nq, self.notion = handle, nq, notion
+        self.result = None
+
+    def wait(self, timeout=None):
+        """dict(depth, count (halfspace), info) once done; raises RRSError with
+        status RRS_E_BUSY if still running after `timeout` seconds."""
+        if self.result is not None:
+            return self.result
+        depth = np.empty(self.nq, dtype=np.float64)
+        count = np.empty(self.nq, dtype=np.int64)
+        info = rrs_request_info()
+        st = load().rrs_wait(self.handle, -1.0 if timeout is None else float(timeout),
+                             depth.ctypes.data_as(ctypes.c_void_p),
+                             count.ctypes.data_as(ctypes.c_void_p), ctypes.byref(info))
+        if st == RRS_E_BUSY:
+            raise RRSError(st, load().rrs_last_error().decode())
+        self.handle = None
+        _check(st)
+        self.result = {"depth": depth, "info": {k: getattr(info, k) for k, _ in info._fields_}}
+        if self.notion == "halfspace":
+            self.result["count"] = count
+        return self.result
+
+
+class Context:
+    """Serving context on one device: a memory budget, `slots` concurrent
+    request streams and a scheduler thread (rrs_ctx_create)."""
+
+    def __init__(self, device=0, slots=0, hbm_budget=0, request_ws_limit=0):
+        cfg = rrs_ctx_config(int(device), int(slots), int(hbm_budget), int(request_ws_limit))
+        h = ctypes.c_void_p()
+        _check(load().rrs_ctx_create(ctypes.byref(cfg), ctypes.byref(h)))
+        self.handle = h
+
+    def put(self, X) -> Dataset:
+        X = np.ascontiguousarray(X, dtype=np.float64)
+        h = ctypes.c_void_p()
+        _check(load().rrs_dataset_put(self.handle, X.ctypes.data_as(ctypes.c_void_p),
+                                      X.shape[0], X.shape[1], ctypes.byref(h)))
+        return Dataset(self, h, X.shape[0], X.shape[1])
+
+    def submit(self, ds: Dataset, notion, Z, K, n_refine, cap_shrink, seed=0, precision="f64",
+               query_offset=0, workspace_limit=0) -> Request:
+        Z = np.ascontiguousarray(Z, dtype=np.float64)
+        o = rrs_opts()
+        o.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+        o.query_offset = int(query_offset)
+        o.workspace_limit = int(workspace_limit)
+        h = ctypes.c_void_p()
+        _check(load().rrs_submit(self.handle, ds.handle, NOTIONS[notion],
+                                 Z.ctypes.data_as(ctypes.c_void_p), Z.shape[0], int(K),
+                                 int(n_refine), float(cap_shrink), int(seed), ctypes.byref(o),
+                                 ctypes.byref(h)))
+        return Request(h, Z.shape[0], notion)
+
+    def stats(self) -> dict:
+        st = rrs_ctx_stats()
+        _check(load().rrs_ctx_get_stats(self.handle, ctypes.byref(st)))
+        return {k: getattr(st, k) for k, _ in st._fields_}
+
+    def close(self):
+        if self.handle is not None:
+            _check(load().rrs_ctx_destroy(self.handle))
+            self.handle = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()

@@ -73,3 +73,26 @@ def test_zero_queries_is_noop():
 def test_debug_directions_validates():
     with pytest.raises(rrs.RRSError):
         rrs.rrs_debug_directions(1, 4, 1, 1.0, 0, 0, np.ones(1))
+
+
+def test_serving_struct_layouts():
+    assert ctypes.sizeof(rrs.rrs_ctx_config) == 24
+    assert ctypes.sizeof(rrs.rrs_request_info) == 40
+    assert ctypes.sizeof(rrs.rrs_ctx_stats) == 64
+
+
+def test_serving_argument_errors_without_device():
+    L = rrs.load()
+    assert L.rrs_ctx_create(None, None) == rrs.RRS_E_INVAL
+    assert L.rrs_ctx_destroy(None) == rrs.RRS_E_INVAL
+    assert L.rrs_wait(None, 0.0, None, None, None) == rrs.RRS_E_INVAL
+    assert L.rrs_dataset_release(None, None) == rrs.RRS_E_INVAL
+    out = ctypes.c_void_p()
+    assert L.rrs_submit(None, None, 0, None, 1, 10, 1, 0.5, 0, None,
+                        ctypes.byref(out)) == rrs.RRS_E_INVAL
+    assert L.rrs_dataset_put(None, None, 10, 2, ctypes.byref(out)) == rrs.RRS_E_INVAL
+    # no device in this process: creating a context fails cleanly
+    import torch
+    if not torch.cuda.is_available():
+        st = L.rrs_ctx_create(None, ctypes.byref(out))
+        assert st != rrs.RRS_OK and out.value is None

@@ -190,23 +190,30 @@ def test_single_hip_runtime_in_process():
 
 
 # --------------------------------------------------------------------------
-# Halfspace depth on the matrix cores (bf16 split + binary64 recheck): the
-# counts, poles and traces must be identical to the binary64 recipe.
+# Halfspace depth on the matrix cores (bf16 split or binary32, each with a
+# binary64 recheck of the uncertain signs): counts, poles and traces must be
+# identical to the binary64 recipe.
 # --------------------------------------------------------------------------
-def test_bf16_c1_halfspace():
+MFMA_EXACT = ["bf16", "f32"]
+
+
+@pytest.mark.parametrize("prec", MFMA_EXACT)
+def test_mfma_c1_halfspace(prec):
     w = workloads.make("c1")
-    _compare("halfspace", w, precision="bf16")
+    _compare("halfspace", w, precision=prec)
 
 
+@pytest.mark.parametrize("prec", MFMA_EXACT)
 @pytest.mark.parametrize("n,d,law", [(700, 2, "gaussian"), (1001, 3, "integer"),
                                      (1500, 7, "exponential"), (900, 33, "mixture"),
                                      (2100, 100, "toeplitz")])
-def test_bf16_halfspace_parity(n, d, law):
+def test_mfma_halfspace_parity(prec, n, d, law):
     w = workloads.small("halfspace", n, d, 20, 240, 6, 0.5, law=law, seed_cfg=n + 3 * d)
-    _compare("halfspace", w, precision="bf16")
+    _compare("halfspace", w, precision=prec)
 
 
-def test_bf16_halfspace_ties_and_far_queries():
+@pytest.mark.parametrize("prec", MFMA_EXACT)
+def test_mfma_halfspace_ties_and_far_queries(prec):
     w = workloads.small("halfspace", 300, 4, 16, 160, 4, 0.5, law="integer", seed_cfg=78)
     Z = w.Z.copy()
     Z[:6] = w.X[:6]
@@ -215,23 +222,45 @@ def test_bf16_halfspace_ties_and_far_queries():
     X = w.X.copy()
     X[100:140] = X[0]
     w.X = X
-    _compare("halfspace", w, precision="bf16")
+    _compare("halfspace", w, precision=prec)
 
 
-def test_bf16_matches_f64_on_c1b_and_offset_data():
+@pytest.mark.parametrize("prec", MFMA_EXACT)
+def test_mfma_matches_f64_on_c1b_and_offset_data(prec):
     w = workloads.make("c1b")
-    _compare("halfspace", w, precision="bf16")
+    _compare("halfspace", w, precision=prec)
     # data far from the origin: the centring by the mean keeps the margin small
     w2 = workloads.small("halfspace", 800, 5, 12, 200, 5, 0.6, law="gaussian", seed_cfg=9)
     w2.X = w2.X + 1e3
     w2.Z = w2.Z + 1e3
-    _compare("halfspace", w2, precision="bf16")
+    _compare("halfspace", w2, precision=prec)
 
 
-def test_bf16_rejected_for_projection():
+def test_f32_plain_halfspace_error_is_reported_and_small():
+    """The plain binary32 form has no recheck: its counts are approximate.
+    On C1 it must agree with the exact counts on almost every query, and it
+    can only be off where projections sit within binary32 rounding of 0."""
+    w = workloads.make("c1")
+    exact = rrs.rrs_depth_halfspace(w.X, w.Z, w.K, w.n_refine, w.cap_shrink, w.rrs_seed)
+    plain = rrs.rrs_depth_halfspace(w.X, w.Z, w.K, w.n_refine, w.cap_shrink, w.rrs_seed,
+                                    precision="f32_plain")
+    diff = np.abs(plain["count"] - exact["count"])
+    _say("f32_plain vs f64 count mismatches:", int((diff > 0).sum()), "max", int(diff.max()))
+    assert (diff == 0).mean() >= 0.9
+    assert diff.max() <= 0.02 * w.n
+    # a single refinement of sphere directions: the same directions, so each
+    # count differs only through sign decisions within the rounding error
+    one = dict(K=200, n_refine=1, cap_shrink=1.0)
+    e1 = rrs.rrs_depth_halfspace(w.X, w.Z, one["K"], 1, 1.0, 5)["count"]
+    p1 = rrs.rrs_depth_halfspace(w.X, w.Z, one["K"], 1, 1.0, 5, precision="f32_plain")["count"]
+    assert np.abs(p1 - e1).max() <= 2
+
+
+@pytest.mark.parametrize("prec", ["bf16", "f32", "f32_plain"])
+def test_mfma_forms_rejected_for_projection(prec):
     w = workloads.small("projection", 100, 3, 2, 20, 2, 0.5)
     with pytest.raises(rrs.RRSError):
-        rrs.rrs_depth_projection(w.X, w.Z, w.K, w.n_refine, w.cap_shrink, precision="bf16")
+        rrs.rrs_depth_projection(w.X, w.Z, w.K, w.n_refine, w.cap_shrink, precision=prec)
 
 
 def test_select_fast_path_dominates_on_centred_columns():
