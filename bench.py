@@ -101,12 +101,93 @@ def cpu_baseline(w, notion, max_queries, per_thread_budget=1.2e8):
             "seconds": dt}
 
 
+def serve_main(args):
+    """Serving stream: requests arrive at their Poisson times and go through
+    one serving context (resident data sets, admission by memory, several
+    requests on the device at once).  Reports whole-stream throughput and
+    the p50/p99 of the submit-to-result latency."""
+    import numpy as np
+    import torch
+
+    from paper_2506_08262_amd import rrs, workloads
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    stream = workloads.c4_stream(args.requests, max_queries=args.max_queries)
+    offered = sum(r.projections for r in stream) / stream[-1].arrival
+    print(f"[bench] serving stream: {len(stream)} requests over {stream[-1].arrival:.3f} s, "
+          f"offered {offered:.3g} projections/s", file=sys.stderr, flush=True)
+    prec = {"halfspace": args.serve_h_precision, "projection": "f64"}
+    with rrs.Context(device=0, slots=args.slots, hbm_budget=args.hbm_budget << 30) as ctx:
+        dss = [ctx.put(r.X) for r in stream]
+        print("[bench] data sets resident", file=sys.stderr, flush=True)
+        # warm-up: one small request per notion (kernel loading, operand prep)
+        for notion in ("halfspace", "projection"):
+            ctx.submit(dss[0], notion, stream[0].Z[:1], 100, 2, 0.5, 0,
+                       precision=prec[notion]).wait()
+        t0 = time.monotonic()
+        reqs = []
+        for i, r in enumerate(stream):
+            delay = t0 + r.arrival - time.monotonic()
+            if delay > 0:
+                time.sleep(delay)
+            reqs.append(ctx.submit(dss[i], r.notion, r.Z, r.K, r.n_refine, r.cap_shrink, i,
+                                   precision=prec[r.notion]))
+        outs = []
+        for i, q in enumerate(reqs):
+            outs.append(q.wait())
+            if (i + 1) % 16 == 0:
+                print(f"[bench] {i + 1}/{len(reqs)} requests done", file=sys.stderr, flush=True)
+        stats = ctx.stats()
+    info = [o["info"] for o in outs]
+    lat = np.array([i["done_s"] - i["submit_s"] for i in info])
+    qwait = np.array([i["admit_s"] - i["submit_s"] for i in info])
+    t_first = min(i["submit_s"] for i in info)
+    t_last = max(i["done_s"] for i in info)
+    proj = float(sum(i["projections"] for i in info))
+    value = proj / (t_last - t_first)
+    line = {
+        "metric": "query·direction·point projections/s; p50/p99 request latency",
+        "value": value,
+        "unit": "projections/s",
+        "n_gpus": 1,
+        "steps": 1,
+        "warmup": 1,
+        "ms_per_step": (t_last - t_first) * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": f"halfspace {prec['halfspace']}, projection f64",
+        "data": "synthetic",
+        "config": {"workload": f"c4: serving stream of {len(stream)} requests, Poisson 200/s, "
+                               "halfspace/projection 1/2 each, own data set per request "
+                               "(n log-uniform [1e3,1e5], d U{3..100}, N(0,I) or t3), "
+                               f"1..{args.max_queries} queries, K in {{1k,5k,10k}}, r=10, "
+                               "alpha=0.5",
+                   "requests": len(stream), "slots": args.slots,
+                   "hbm_budget_gib": args.hbm_budget},
+        "latency_ms": {"p50": float(np.percentile(lat, 50) * 1e3),
+                       "p99": float(np.percentile(lat, 99) * 1e3),
+                       "mean": float(lat.mean() * 1e3),
+                       "queue_wait_p50": float(np.percentile(qwait, 50) * 1e3)},
+        "offered_load": offered,
+        "achieved_over_offered": value / offered,
+        "serving_stats": stats,
+        "roofline": None,
+        "cpu_baseline": None,
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="c2", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="c2", choices=sorted(WORKLOADS) + ["c4"])
+    ap.add_argument("--requests", type=int, default=64, help="c4: requests in the stream")
+    ap.add_argument("--max-queries", type=int, default=1000, help="c4: query cap per request")
+    ap.add_argument("--slots", type=int, default=4, help="c4: concurrent requests")
+    ap.add_argument("--hbm-budget", type=int, default=64, help="c4: serving budget in GiB")
+    ap.add_argument("--serve-h-precision", default="bf16", help="c4: halfspace precision")
     ap.add_argument("--precision", default="f64", choices=["f64", "f32", "bf16", "f32_plain"],
                     help="projection arithmetic (matrix-core forms: halfspace depth only)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -119,6 +200,10 @@ def main():
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (queries shard "
               f"across GPUs without communication; run one process per GPU)", file=sys.stderr)
         sys.exit(2)
+
+    if args.workload == "c4":
+        serve_main(args)
+        return
 
     import torch
 

@@ -8,8 +8,8 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "librrs.so")
-SOURCES = ["rrs_kernels.hip", "rrs_select.hip", "rrs_mfma.hip", "rrs_engine.hip", "rrs_api.hip",
-           "rrs_serve.hip"]
+SOURCES = ["rrs_kernels.hip", "rrs_select.hip", "rrs_select_rc.hip", "rrs_mfma.hip",
+           "rrs_engine.hip", "rrs_api.hip", "rrs_serve.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

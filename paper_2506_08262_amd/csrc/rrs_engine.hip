@@ -106,7 +106,7 @@ struct ProfScope {
 size_t data_bytes(int64_t n, int64_t d, int prec)
 {
     const int64_t ldx = (n + 511) / 512 * 512;
-    size_t sizes[5] = {(size_t)d * ldx * 8, 0, 0, 0, 0};
+    size_t sizes[6] = {(size_t)d * ldx * 8, 0, 0, 0, 0, 0};
     if (prec >= 0) {
         const int64_t kp = mfma_kpad(prec, d);
         const size_t eb = mfma_elem_bytes(prec);
@@ -114,8 +114,9 @@ size_t data_bytes(int64_t n, int64_t d, int prec)
         sizes[2] = (size_t)n * kp * eb;
         sizes[3] = mfma_terms(prec) == 2 ? (size_t)n * kp * eb : 0;
         sizes[4] = (size_t)n * 4;
+        sizes[5] = 64;
     }
-    return carve_size(sizes, 5);
+    return carve_size(sizes, 6);
 }
 
 hipError_t data_prepare(DataDev &D, void *mem, int prec, hipStream_t st)
@@ -132,14 +133,16 @@ hipError_t data_prepare(DataDev &D, void *mem, int prec, hipStream_t st)
         D.A0 = cv.take<char>((size_t)n * kp * eb);
         D.A1 = mfma_terms(prec) == 2 ? (void *)cv.take<char>((size_t)n * kp * eb) : nullptr;
         D.anorm = cv.take<float>((size_t)n);
+        D.amax = cv.take<float>(16);
     } else {
         D.xbar = nullptr;
         D.A0 = D.A1 = nullptr;
         D.anorm = nullptr;
+        D.amax = nullptr;
     }
     hipError_t e = launch_transpose(D.X, n, d, D.ldx, D.XT, st);
     if (e != hipSuccess || prec < 0) return e;
-    return launch_mfma_prep(prec, D.X, n, d, D.xbar, D.A0, D.A1, D.anorm, st);
+    return launch_mfma_prep(prec, D.X, n, d, D.xbar, D.A0, D.A1, D.anorm, D.amax, st);
 }
 
 int job_mfma_prec(int precision)
@@ -167,9 +170,6 @@ rrs_status job_validate(const JobSpec &s, int64_t n, int64_t d)
         s.precision != RRS_BF16_RECHECK && s.precision != RRS_F32_PLAIN)
         return fail(RRS_E_INVAL, "unknown precision %d", s.precision);
     const bool mfma = s.precision != RRS_F64;
-    if (mfma && s.notion != NOTION_HALFSPACE)
-        return fail(RRS_E_INVAL, "precision %d is available for halfspace depth only",
-                    s.precision);
     if (mfma && ((s.K + s.r - 1) / s.r >= 65536 || s.nq > 65535))
         return fail(RRS_E_INVAL,
                     "matrix-core precisions need ceil(K/n_refine) < 65536 directions and at "
@@ -195,14 +195,17 @@ int job_sizes(const JobSpec &s, int64_t n, int64_t d, const Plan &p, int64_t qb,
     sz[k++] = (size_t)qb * 8;                                   // best_d
     sz[k++] = (size_t)qb * 8;                                   // best_c
     sz[k++] = half ? (size_t)qb * p.ldm * 2 * 4 : 0;            // cnt
-    sz[k++] = half ? 0 : (size_t)qb * p.m * n * 8;              // T
+    sz[k++] = (half || mfma) ? 0 : (size_t)qb * p.m * n * 8;    // T (binary64)
     sz[k++] = half ? 0 : (size_t)qb * p.ldm * 8;                // Dj
     sz[k++] = 64;                                               // stats
     sz[k++] = mfma ? (size_t)qb * p.ldb * p.kp * p.eb : 0;      // B0
     sz[k++] = (mfma && p.terms == 2) ? (size_t)qb * p.ldb * p.kp * p.eb : 0;  // B1
-    sz[k++] = mfma ? (size_t)qb * p.ldb * 4 : 0;                // cmarg
-    sz[k++] = mfma ? (size_t)p.qcap * 8 : 0;                    // queue
+    sz[k++] = (mfma && half) ? (size_t)qb * p.ldb * 4 : 0;      // cmarg
+    sz[k++] = (mfma && half) ? (size_t)p.qcap * 8 : 0;          // queue
     sz[k++] = 64;                                               // qctl
+    sz[k++] = (mfma && !half) ? (size_t)qb * p.m * n * 4 : 0;   // S (binary32)
+    sz[k++] = (mfma && !half) ? (size_t)qb * p.ldb * 8 : 0;     // cq
+    sz[k++] = (mfma && !half) ? (size_t)qb * p.ldb * 8 : 0;     // eq
     return k;
 }
 
@@ -234,7 +237,7 @@ rrs_status job_plan(const JobSpec &s, int64_t n, int64_t d, size_t limit, Plan *
     size_t sz[16];
     auto bytes = [&](int64_t qb) {
         Plan t = p;
-        t.qcap = p.prec >= 0 ? job_qcap(p, n, qb) : 0;
+        t.qcap = (p.prec >= 0 && s.notion == NOTION_HALFSPACE) ? job_qcap(p, n, qb) : 0;
         const int k = job_sizes(s, n, d, t, qb, sz);
         return carve_size(sz, k);
     };
@@ -250,7 +253,7 @@ rrs_status job_plan(const JobSpec &s, int64_t n, int64_t d, size_t limit, Plan *
         lo = hi;
     }
     p.qb = lo;
-    p.qcap = p.prec >= 0 ? job_qcap(p, n, p.qb) : 0;
+    p.qcap = (p.prec >= 0 && s.notion == NOTION_HALFSPACE) ? job_qcap(p, n, p.qb) : 0;
     p.ws_bytes = bytes(p.qb);
     *out = p;
     return RRS_OK;
@@ -282,14 +285,14 @@ rrs_status enqueue_job(const JobSpec &s, const DataDev &D, const Plan &p, const 
     float *cmarg = cv.take<float>(sz[10] / 4);
     uint64_t *queue = cv.take<uint64_t>(sz[11] / 8);
     uint32_t *qctl = cv.take<uint32_t>(16);  // [0] queue length, [1] overflow flag
+    float *S32 = cv.take<float>(sz[13] / 4);
+    double *cq = cv.take<double>(sz[14] / 8);
+    double *eq = cv.take<double>(sz[15] / 8);
     if (stats_out) *stats_out = stats;
     if (profiling) RRS_HIP_TRY(launch_fill_u32(stats, 16, 0u, st));
 
     // zero the direction padding once (the generator writes j < m only)
     RRS_HIP_TRY(launch_fill_u32((uint32_t *)UT, qb * d * ldm * 2, 0u, st));
-    int dev = 0;
-    RRS_HIP_TRY(hipGetDevice(&dev));
-    const bool lds = !half && n <= select_lds_max_n(dev);
     for (int64_t q0 = 0; q0 < nq; q0 += qb) {
         const int64_t nb = (nq - q0 < qb) ? nq - q0 : qb;
         const double *Zb = io.Z + q0 * d;
@@ -306,8 +309,8 @@ rrs_status enqueue_job(const JobSpec &s, const DataDev &D, const Plan &p, const 
             if (half && mfma) {
                 RRS_HIP_TRY(launch_fill_u32(cnt, nb * ldm * 2, 0u, st));
                 RRS_HIP_TRY(launch_fill_u32(qctl, 16, 0u, st));
-                RRS_HIP_TRY(launch_mfma_dirs(p.prec, UT, d, m, ldm, ldb, nb, Zb, D.xbar, B0, B1,
-                                             cmarg, st));
+                RRS_HIP_TRY(launch_mfma_dirs(p.prec, true, UT, d, m, ldm, ldb, nb, Zb, D.xbar, B0,
+                                             B1, cmarg, D.amax, nullptr, nullptr, st));
                 MfmaArgs ma{p.prec, D.A0,   D.A1,   D.anorm, n,    d,    B0,
                             B1,     cmarg,  m,      ldm,     ldb,  nb,   cnt,
                             queue,  qctl,   p.qcap, qctl + 1, D.X, Zb,   UT,
@@ -325,6 +328,19 @@ rrs_status enqueue_job(const JobSpec &s, const DataDev &D, const Plan &p, const 
                     pa.only_if = qctl + 1;
                     RRS_HIP_TRY(launch_proj_f64(pa, true, st));
                 }
+            } else if (mfma) {
+                // projection / APD from binary32 projections on the matrix cores
+                RRS_HIP_TRY(launch_mfma_dirs(p.prec, false, UT, d, m, ldm, ldb, nb, Zb, D.xbar,
+                                             B0, B1, nullptr, D.amax, cq, eq, st));
+                {
+                    ProfScope ps(prof, K_MFMA, proj_units, st);
+                    RRS_HIP_TRY(launch_mfma_store(p.prec, D.A0, D.A1, n, d, B0, B1, m, ldb, nb,
+                                                  S32, st));
+                }
+                SelectRcArgs ra{S32, n,  m,  ldm, ldb, nb, cq, eq, D.X, d, Zb, UT, Dj,
+                                profiling ? stats : nullptr};
+                ProfScope ps(prof, K_SELECT, proj_units, st);
+                RRS_HIP_TRY(launch_select_rc(ra, s.notion, p.prec != MFMA_F32_PLAIN, st));
             } else if (half) {
                 RRS_HIP_TRY(launch_fill_u32(cnt, nb * ldm * 2, 0u, st));
                 ProfScope ps(prof, K_PROJ, proj_units, st);
@@ -339,7 +355,7 @@ rrs_status enqueue_job(const JobSpec &s, const DataDev &D, const Plan &p, const 
                 if (n <= select_reg_max_n())
                     RRS_HIP_TRY(launch_select_reg(sa, s.notion, st));
                 else
-                    RRS_HIP_TRY(launch_select(sa, s.notion, lds, st));
+                    RRS_HIP_TRY(launch_select_stream(sa, s.notion, st));
             }
             ArgminArgs aa{m, ldm, d, nb, cnt, Dj, UT, pole, best_d, best_c,
                           io.trace ? io.trace + q0 * r * 3 : nullptr, l, r};

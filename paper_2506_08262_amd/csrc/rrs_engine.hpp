@@ -78,6 +78,7 @@ struct DataDev {
     double *xbar = nullptr;      // [d] column means
     void *A0 = nullptr, *A1 = nullptr;  // [n][kp] centred operands
     float *anorm = nullptr;      // [n] norm bounds of the centred points
+    float *amax = nullptr;       // largest of them (one value)
 };
 
 // Bytes of the prepared data beyond X itself: XT, plus the operands of one

@@ -59,6 +59,19 @@ struct SelectArgs {
     uint32_t *stats;  // optional [2]: pairs resolved by the bracket / the fallback
 };
 
+// Projection / APD depth from binary32 projections (rrs_select_rc.hip).
+struct SelectRcArgs {
+    const float *S;            // [qb][m][n] s_ij = a_i.u_j
+    int64_t n, m, ldm, ldb, qb;
+    const double *cq, *eq;     // [qb][ldb] centring terms and error bounds
+    const double *X;           // [n][d] binary64 data (recompute)
+    int64_t d;
+    const double *Z;           // [qb][d]
+    const double *UT;          // [qb][d][ldm]
+    double *Dj;
+    uint32_t *stats;
+};
+
 struct ArgminArgs {
     int64_t m, ldm, d, qb;
     const uint32_t *cnt;
@@ -80,16 +93,22 @@ int64_t select_lds_max_n(int device);
 hipError_t launch_select(const SelectArgs &a, int notion, bool lds, hipStream_t st);
 int64_t select_reg_max_n();
 hipError_t launch_select_reg(const SelectArgs &a, int notion, hipStream_t st);
+hipError_t launch_select_stream(const SelectArgs &a, int notion, hipStream_t st);
+hipError_t launch_select_rc(const SelectRcArgs &a, int notion, bool exact, hipStream_t st);
 hipError_t launch_argmin(const ArgminArgs &a, bool half, hipStream_t st);
 int64_t mfma_kpad(int prec, int64_t d);
 size_t mfma_elem_bytes(int prec);
 int mfma_terms(int prec);
 void mfma_margins(int prec, int64_t d, int64_t kp, double *kappa, double *canon);
 hipError_t launch_mfma_prep(int prec, const double *X, int64_t n, int64_t d, double *xbar,
-                            void *A0, void *A1, float *anorm, hipStream_t st);
-hipError_t launch_mfma_dirs(int prec, const double *UT, int64_t d, int64_t m, int64_t ldm,
-                            int64_t ldb, int64_t qb, const double *Zb, const double *xbar,
-                            void *B0, void *B1, float *cmarg, hipStream_t st);
+                            void *A0, void *A1, float *anorm, float *amax, hipStream_t st);
+hipError_t launch_mfma_dirs(int prec, bool fold, const double *UT, int64_t d, int64_t m,
+                            int64_t ldm, int64_t ldb, int64_t qb, const double *Zb,
+                            const double *xbar, void *B0, void *B1, float *cmarg,
+                            const float *amax, double *cq, double *eq, hipStream_t st);
+hipError_t launch_mfma_store(int prec, const void *A0, const void *A1, int64_t n, int64_t d,
+                             const void *B0, const void *B1, int64_t m, int64_t ldb, int64_t qb,
+                             float *S, hipStream_t st);
 hipError_t launch_mfma_gemm(const MfmaArgs &a, hipStream_t st);
 hipError_t launch_mfma_recheck(const MfmaArgs &a, hipStream_t st);
 constexpr int kMfmaCols = 64;  // directions per matrix-core workgroup

@@ -64,7 +64,8 @@ __global__ __launch_bounds__(256) void k_prep_data(const double *__restrict__ X,
                                                    int64_t d, int64_t kp,
                                                    const double *__restrict__ xbar,
                                                    void *__restrict__ A0, void *__restrict__ A1,
-                                                   float *__restrict__ anorm)
+                                                   float *__restrict__ anorm,
+                                                   float *__restrict__ amax)
 {
     const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (i >= n) return;
@@ -90,19 +91,27 @@ __global__ __launch_bounds__(256) void k_prep_data(const double *__restrict__ X,
     // upper bound of the norm, rounded up to binary32
     const float nf = (float)sqrt(ss);
     anorm[i] = nf * (1.0f + 1e-6f);
+    // largest norm bound (non-negative floats order like their bit patterns)
+    atomicMax((int *)amax, __float_as_int(anorm[i]));
 }
 
 // Per refinement: the directions (binary64, [q][d][ldm] in UT) in the GEMM's
-// operand format with the centring term folded in; cmarg[q][j] = kappa |c_j|
-// + slack (binary32, rounded up).
-template <int PREC>
+// operand format.  FOLD (sign counts): the centring term is folded in and
+// cmarg[q][j] = kappa |c_j| + slack (binary32, rounded up).  Otherwise (stored
+// projections): the centring columns are zero, cq[q][j] = c_j and eq[q][j]
+// bounds |(s_ij - c_j) - t_ij| for every point i, with t_ij the recipe's
+// binary64 projection: kappa max|a| + canon (max|a| + 2 |z - xbar|).
+template <int PREC, bool FOLD>
 __global__ __launch_bounds__(64) void k_prep_dirs(const double *__restrict__ UT, int64_t d,
                                                   int64_t m, int64_t ldm, int64_t ldb,
                                                   int64_t kp, const double *__restrict__ Zb,
                                                   const double *__restrict__ xbar, double kappa,
                                                   double canon, void *__restrict__ B0,
                                                   void *__restrict__ B1,
-                                                  float *__restrict__ cmarg)
+                                                  float *__restrict__ cmarg,
+                                                  const float *__restrict__ amax,
+                                                  double *__restrict__ cq,
+                                                  double *__restrict__ eq)
 {
     const int64_t j = (int64_t)blockIdx.x * 64 + threadIdx.x;
     const int64_t qi = blockIdx.y;
@@ -120,7 +129,12 @@ __global__ __launch_bounds__(64) void k_prep_dirs(const double *__restrict__ UT,
                 bf[c] = 0.0f;
             }
         }
-        cmarg[qi * ldb + j] = 0.0f;
+        if (FOLD) {
+            cmarg[qi * ldb + j] = 0.0f;
+        } else {
+            cq[qi * ldb + j] = 0.0;
+            eq[qi * ldb + j] = 0.0;
+        }
         return;
     }
     const double *u = UT + qi * d * ldm + j;
@@ -139,15 +153,15 @@ __global__ __launch_bounds__(64) void k_prep_dirs(const double *__restrict__ UT,
             bf[c] = (float)uc;
         }
     }
-    int64_t c0;
-    if (PREC == MFMA_BF16) {
+    int64_t c0 = d;
+    if (FOLD && PREC == MFMA_BF16) {
         const __bf16 ch = to_bf16(-cj);
         bh[d] = ch;
         bh[d + 1] = to_bf16(-cj - from_bf16(ch));
         bl[d] = (__bf16)0.0f;
         bl[d + 1] = (__bf16)0.0f;
         c0 = d + 2;
-    } else {
+    } else if (FOLD) {
         bf[d] = (float)(-cj);
         c0 = d + 1;
     }
@@ -162,8 +176,14 @@ __global__ __launch_bounds__(64) void k_prep_dirs(const double *__restrict__ UT,
     // margin part that depends on the direction only: kappa |c_j| plus the
     // binary64 recipe's own error through |z - xbar|; the data part
     // kappa' |a_i| is added per element
-    const double mc = kappa * fabs(cj) + canon * sqrt(bn) * 1.000001 + 1e-300;
-    cmarg[qi * ldb + j] = (float)mc * (1.0f + 1e-6f);
+    if (FOLD) {
+        const double mc = kappa * fabs(cj) + canon * sqrt(bn) * 1.000001 + 1e-300;
+        cmarg[qi * ldb + j] = (float)mc * (1.0f + 1e-6f);
+    } else {
+        const double am = (double)*amax;
+        cq[qi * ldb + j] = cj;
+        eq[qi * ldb + j] = (kappa * am + canon * (am + 2.0 * sqrt(bn) * 1.000001)) * 1.000001;
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -180,21 +200,13 @@ __global__ __launch_bounds__(64) void k_prep_dirs(const double *__restrict__ UT,
 //   both: accumulator r holds row (r / 4) 8 + 4 lh + r % 4 of column lr.
 // ---------------------------------------------------------------------------
 template <int PREC>
-__global__ __launch_bounds__(256) void k_gemm_sign(
-    const void *__restrict__ A0, const void *__restrict__ A1,
-    const float *__restrict__ anorm, int64_t n, int64_t kp,
-    const void *__restrict__ B0, const void *__restrict__ B1,
-    const float *__restrict__ cmarg, int64_t m, int64_t ldm, int64_t ldb, float kappa_a,
-    uint32_t *__restrict__ cnt, uint64_t *__restrict__ queue, uint32_t *__restrict__ qcount,
-    uint64_t qcap)
+__device__ __forceinline__ void gemm_tile(const void *__restrict__ A0,
+                                          const void *__restrict__ A1, int64_t n, int64_t kp,
+                                          const void *__restrict__ B0,
+                                          const void *__restrict__ B1, int64_t ldb, int64_t qi,
+                                          int64_t j0, int64_t row0, int lr, int lh,
+                                          f32x16 (&acc)[kNJ])
 {
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int64_t qi = blockIdx.y;
-    const int64_t j0 = (int64_t)blockIdx.x * (32 * kNJ);
-    const int64_t row0 = (int64_t)blockIdx.z * (kRowsPerWave * kWaves) + wave * kRowsPerWave;
-    const int lr = lane & 31, lh = lane >> 5;
-
-    f32x16 acc[kNJ];
 #pragma unroll
     for (int t = 0; t < kNJ; ++t)
 #pragma unroll
@@ -244,6 +256,24 @@ __global__ __launch_bounds__(256) void k_gemm_sign(
             }
         }
     }
+}
+
+template <int PREC>
+__global__ __launch_bounds__(256) void k_gemm_sign(
+    const void *__restrict__ A0, const void *__restrict__ A1,
+    const float *__restrict__ anorm, int64_t n, int64_t kp,
+    const void *__restrict__ B0, const void *__restrict__ B1,
+    const float *__restrict__ cmarg, int64_t m, int64_t ldm, int64_t ldb, float kappa_a,
+    uint32_t *__restrict__ cnt, uint64_t *__restrict__ queue, uint32_t *__restrict__ qcount,
+    uint64_t qcap)
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int64_t qi = blockIdx.y;
+    const int64_t j0 = (int64_t)blockIdx.x * (32 * kNJ);
+    const int64_t row0 = (int64_t)blockIdx.z * (kRowsPerWave * kWaves) + wave * kRowsPerWave;
+    const int lr = lane & 31, lh = lane >> 5;
+    f32x16 acc[kNJ];
+    gemm_tile<PREC>(A0, A1, n, kp, B0, B1, ldb, qi, j0, row0, lr, lh, acc);
 
     // epilogue: per lane, one column per tile, 16 rows
     constexpr bool kPlain = PREC == MFMA_F32_PLAIN;
@@ -297,6 +327,44 @@ __global__ __launch_bounds__(256) void k_gemm_sign(
 #pragma unroll
         for (int wv = 0; wv < kWaves; ++wv) s += red[wv][jj][w];
         if (j < m && s) atomicAdd(&cnt[(qi * ldm + j) * 2 + w], s);
+    }
+}
+
+// GEMM with a store epilogue: the centred projections s_ij = a_i.u_j
+// (binary32) of the batch, column (query, direction) after column, for the
+// selects of projection and asymmetric projection depth.  Lane lr writes
+// rows (r / 4) 8 + 4 lh .. + 3 of its column as one 16-byte store.
+template <int PREC>
+__global__ __launch_bounds__(256) void k_gemm_store(const void *__restrict__ A0,
+                                                    const void *__restrict__ A1, int64_t n,
+                                                    int64_t kp, const void *__restrict__ B0,
+                                                    const void *__restrict__ B1, int64_t m,
+                                                    int64_t ldb, float *__restrict__ S)
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int64_t qi = blockIdx.y;
+    const int64_t j0 = (int64_t)blockIdx.x * (32 * kNJ);
+    const int64_t row0 = (int64_t)blockIdx.z * (kRowsPerWave * kWaves) + wave * kRowsPerWave;
+    const int lr = lane & 31, lh = lane >> 5;
+    f32x16 acc[kNJ];
+    gemm_tile<PREC>(A0, A1, n, kp, B0, B1, ldb, qi, j0, row0, lr, lh, acc);
+#pragma unroll
+    for (int t = 0; t < kNJ; ++t) {
+        const int64_t j = j0 + 32 * t + lr;
+        if (j >= m) continue;
+        float *col = S + (qi * m + j) * n;
+#pragma unroll
+        for (int g = 0; g < 4; ++g) {
+            const int64_t i = row0 + g * 8 + lh * 4;
+            if (i + 3 < n && (n & 3) == 0) {
+                f32x4 v = {acc[t][4 * g], acc[t][4 * g + 1], acc[t][4 * g + 2], acc[t][4 * g + 3]};
+                *(f32x4 *)(col + i) = v;
+            } else {
+#pragma unroll
+                for (int e = 0; e < 4; ++e)
+                    if (i + e < n) col[i + e] = acc[t][4 * g + e];
+            }
+        }
     }
 }
 
@@ -381,36 +449,65 @@ size_t mfma_elem_bytes(int prec) { return prec == MFMA_BF16 ? 2 : 4; }
 int mfma_terms(int prec) { return prec == MFMA_BF16 ? 2 : 1; }
 
 hipError_t launch_mfma_prep(int prec, const double *X, int64_t n, int64_t d, double *xbar,
-                            void *A0, void *A1, float *anorm, hipStream_t st)
+                            void *A0, void *A1, float *anorm, float *amax, hipStream_t st)
 {
+    hipError_t e = launch_fill_u32((uint32_t *)amax, 1, 0u, st);
+    if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_col_mean, dim3((unsigned)d), dim3(256), 0, st, X, n, d, xbar);
-    hipError_t e = hipGetLastError();
+    e = hipGetLastError();
     if (e != hipSuccess) return e;
     const dim3 grid((unsigned)((n + 255) / 256));
     const int64_t kp = mfma_kpad(prec, d);
     if (prec == MFMA_BF16)
         hipLaunchKernelGGL(k_prep_data<MFMA_BF16>, grid, dim3(256), 0, st, X, n, d, kp, xbar,
-                           A0, A1, anorm);
+                           A0, A1, anorm, amax);
     else
         hipLaunchKernelGGL(k_prep_data<MFMA_F32>, grid, dim3(256), 0, st, X, n, d, kp, xbar, A0,
-                           A1, anorm);
+                           A1, anorm, amax);
     return hipGetLastError();
 }
 
-hipError_t launch_mfma_dirs(int prec, const double *UT, int64_t d, int64_t m, int64_t ldm,
-                            int64_t ldb, int64_t qb, const double *Zb, const double *xbar,
-                            void *B0, void *B1, float *cmarg, hipStream_t st)
+hipError_t launch_mfma_dirs(int prec, bool fold, const double *UT, int64_t d, int64_t m,
+                            int64_t ldm, int64_t ldb, int64_t qb, const double *Zb,
+                            const double *xbar, void *B0, void *B1, float *cmarg,
+                            const float *amax, double *cq, double *eq, hipStream_t st)
 {
     double kappa, canon;
     const int64_t kp = mfma_kpad(prec, d);
     mfma_margins(prec, d, kp, &kappa, &canon);
     dim3 grid((unsigned)((ldb + 63) / 64), (unsigned)qb);
+#define RRS_DIRS(P, F)                                                                        \
+    hipLaunchKernelGGL((k_prep_dirs<P, F>), grid, dim3(64), 0, st, UT, d, m, ldm, ldb, kp, Zb, \
+                       xbar, kappa, canon, B0, B1, cmarg, amax, cq, eq)
+    if (prec == MFMA_BF16) {
+        if (fold)
+            RRS_DIRS(MFMA_BF16, true);
+        else
+            RRS_DIRS(MFMA_BF16, false);
+    } else {
+        if (fold)
+            RRS_DIRS(MFMA_F32, true);
+        else
+            RRS_DIRS(MFMA_F32, false);
+    }
+#undef RRS_DIRS
+    return hipGetLastError();
+}
+
+hipError_t launch_mfma_store(int prec, const void *A0, const void *A1, int64_t n, int64_t d,
+                             const void *B0, const void *B1, int64_t m, int64_t ldb, int64_t qb,
+                             float *S, hipStream_t st)
+{
+    const int64_t kp = mfma_kpad(prec, d);
+    dim3 grid((unsigned)((m + 32 * kNJ - 1) / (32 * kNJ)), (unsigned)qb,
+              (unsigned)((n + kRowsPerWave * kWaves - 1) / (kRowsPerWave * kWaves)));
+    if (ldb < (int64_t)grid.x * 32 * kNJ) return hipErrorInvalidValue;
     if (prec == MFMA_BF16)
-        hipLaunchKernelGGL(k_prep_dirs<MFMA_BF16>, grid, dim3(64), 0, st, UT, d, m, ldm, ldb, kp,
-                           Zb, xbar, kappa, canon, B0, B1, cmarg);
+        hipLaunchKernelGGL(k_gemm_store<MFMA_BF16>, grid, dim3(256), 0, st, A0, A1, n, kp, B0, B1,
+                           m, ldb, S);
     else
-        hipLaunchKernelGGL(k_prep_dirs<MFMA_F32>, grid, dim3(64), 0, st, UT, d, m, ldm, ldb, kp,
-                           Zb, xbar, kappa, canon, B0, B1, cmarg);
+        hipLaunchKernelGGL(k_gemm_store<MFMA_F32>, grid, dim3(256), 0, st, A0, A1, n, kp, B0, B1,
+                           m, ldb, S);
     return hipGetLastError();
 }
 

@@ -31,10 +31,13 @@
 
 #include "rrs_device.hpp"
 #include "rrs_launch.hpp"
+#include "rrs_select_common.hpp"
 
 namespace rrs {
 
 namespace {
+
+using namespace sel;
 
 constexpr int kT = 256;        // lanes per workgroup
 constexpr int kBins = 256;     // bins of the bracket
@@ -63,75 +66,6 @@ struct RegShared {
     uint64_t rresult;
 };
 
-// Value of column entry t in phase PH and whether it takes part (used by the
-// global-memory fallback; identical to the in-place register transforms).
-template <int PH>
-__device__ __forceinline__ bool phase_val(double t, double med, double &x)
-{
-    if (PH == 0) {
-        x = t;
-        return true;
-    } else if (PH == 1) {
-        x = fabs(t - med);
-        return true;
-    } else {
-        x = t - med;
-        return x > 0.0;
-    }
-}
-
-// 32-bit key of a register value in phase PH.  Phase 0 values carry a sign;
-// phases 1 and 2 are >= 0 or NaN, whose high words already order correctly.
-// Returns 0xFFFFFFFF for NaN (and +inf in phase 0), which never takes part.
-template <int PH>
-__device__ __forceinline__ uint32_t key32(double x)
-{
-    const uint32_t hi = (uint32_t)__double2hiint(x);
-    if (PH == 0) {
-        const uint32_t m = (uint32_t)((int32_t)hi >> 31) | 0x80000000u;
-        return hi ^ m;
-    }
-    return hi;
-}
-
-template <int PH>
-__device__ __forceinline__ bool key_takes_part(uint32_t k);
-
-// Wave-uniform broadcast of lane `src`'s double.
-__device__ __forceinline__ double lane_bcast(double x, int src)
-{
-    const int lo = __double2loint(x), hi = __double2hiint(x);
-    return __hiloint2double(__builtin_amdgcn_readlane(hi, src), __builtin_amdgcn_readlane(lo, src));
-}
-
-// Key used for binning.  With mag the high word of |x| (monotone in |x|):
-// magnitudes below tau map to the key of zero, larger ones are offset by tau
-// so that they start right next to it,
-//   |x| < tau: 2^31;   x >= tau: 2^31 + 1 + (mag - tau);
-//   x <= -tau: 2^31 - 1 - (mag - tau)           (phase 0 only).
-// Monotone in x, and a bracket that straddles zero spends its key range on
-// the magnitudes it holds instead of on the empty logarithmic range of tiny
-// ones.  NaN keys exceed every finite key.
-template <int PH>
-__device__ __forceinline__ uint32_t bin_key(double x, uint32_t tau)
-{
-    const uint32_t hi = (uint32_t)__double2hiint(x);
-    const uint32_t mag = hi & 0x7FFFFFFFu;
-    const uint32_t dd = mag - tau;
-    if (PH == 0) {
-        if (mag < tau) return 0x80000000u;
-        return (hi >> 31) ? 0x7FFFFFFFu - dd : 0x80000001u + dd;
-    }
-    return mag < tau ? 0u : 1u + dd;
-}
-
-template <int PH>
-__device__ __forceinline__ bool key_takes_part(uint32_t k)
-{
-    // finite values: phase 0 keys < 0xFFF00000, phases 1/2 keys < 0x7FF00000
-    return PH == 0 ? k < 0xFFF00000u : k < 0x7FF00000u;
-}
-
 // Makes every register of the column opaque to the optimiser, so that values
 // derived from it before this point are not kept live after it.
 template <int VPT>
@@ -139,44 +73,6 @@ __device__ __forceinline__ void launder(double (&vals)[VPT])
 {
 #pragma unroll
     for (int v = 0; v < VPT; ++v) asm volatile("" : "+v"(vals[v]));
-}
-
-// Bucket of a 256-bucket histogram holding rank k when the values below the
-// histogram number `base`: lane `lane` of a wave owns buckets 4 lane .. 4 lane
-// + 3 and reports found = true when the rank falls in them.
-__device__ __forceinline__ void scan_hist(const uint32_t *hist, uint64_t base, uint64_t k,
-                                          uint32_t &bin, uint32_t &before_in_bin,
-                                          uint32_t &cnt, bool &found)
-{
-    const int lane = threadIdx.x & 63;
-    const uint32_t h0 = hist[4 * lane], h1 = hist[4 * lane + 1];
-    const uint32_t h2 = hist[4 * lane + 2], h3 = hist[4 * lane + 3];
-    const uint32_t tot = h0 + h1 + h2 + h3;
-    uint32_t incl = tot;
-    for (int off = 1; off < 64; off <<= 1) {
-        const uint32_t o = (uint32_t)__shfl_up((int)incl, off);
-        if (lane >= off) incl += o;
-    }
-    const uint64_t ex = base + incl - tot;
-    found = ex <= k && k < ex + tot;
-    uint64_t c = ex;
-    if (k < c + h0) {
-        bin = 4 * lane;
-        cnt = h0;
-    } else if (k < c + h0 + h1) {
-        bin = 4 * lane + 1;
-        cnt = h1;
-        c += h0;
-    } else if (k < c + h0 + h1 + h2) {
-        bin = 4 * lane + 2;
-        cnt = h2;
-        c += h0 + h1;
-    } else {
-        bin = 4 * lane + 3;
-        cnt = h3;
-        c += h0 + h1 + h2;
-    }
-    before_in_bin = found ? (uint32_t)(k - c) : 0u;
 }
 
 // ---------------------------------------------------------------------------
@@ -545,6 +441,255 @@ __global__ __launch_bounds__(kT) void k_select_reg(const double *__restrict__ T,
     if (tid == 0) Dj[qi * ldm + j] = D;
 }
 
+// ---------------------------------------------------------------------------
+// Streaming form for columns too long for the registers: the same bracket /
+// bin / candidate passes, each pass re-reading the column from global memory
+// (4 loads in flight per lane) and applying the phase on the fly.
+// ---------------------------------------------------------------------------
+constexpr int kUnroll = 4;
+
+template <int PH>
+__device__ void select_pair_stream(const double *__restrict__ col, int64_t n, double med,
+                                   uint64_t cnt, uint64_t k, bool pair, double &a, double &b,
+                                   RegShared &sh, uint32_t *stats)
+{
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    sh.hist[tid] = 0;
+    if (tid < 64) sh.srank[tid] = 0;
+    if (tid == 0) {
+        sh.below = 0;
+        sh.ncandA = 0;
+        sh.ncandB = 0;
+    }
+    // sample: 64 entries spread evenly over the column
+    if (tid < 64) {
+        const int64_t i = ((2 * (int64_t)tid + 1) * n) / 128;
+        double x = 0.0;
+        const bool part = phase_val<PH>(col[i], med, x);
+        const uint32_t kx = key32<PH>(x);
+        sh.skey[tid] = (part && key_takes_part<PH>(kx)) ? kx : 0xFFFFFFFFu;
+        sh.sval[tid] = x;
+    }
+    __syncthreads();
+    {
+        const uint32_t mine = sh.skey[lane];
+        uint32_t part = 0;
+#pragma unroll
+        for (int jj = 0; jj < 16; ++jj) {
+            const int o = wave * 16 + jj;
+            const uint32_t ko = sh.skey[o];
+            part += (ko < mine || (ko == mine && o < lane)) ? 1u : 0u;
+        }
+        atomicAdd(&sh.srank[lane], part);
+    }
+    __syncthreads();
+    if (tid < 64) {
+        const uint32_t kx = sh.skey[lane];
+        const bool ok = kx != 0xFFFFFFFFu;
+        const uint32_t rank = sh.srank[lane];
+        const uint32_t S = (uint32_t)__popcll(__ballot(ok));
+        int fast0 = (S >= 16 && cnt > 0) ? 1 : 0;
+        uint32_t Lk = 0, Hk = 0, tau = 0;
+        if (fast0) {
+            const double f = ((double)k + 0.5) / (double)cnt;
+            const double pos = f * (double)S;
+            const double del = 2.5 * sqrt((double)S * f * (1.0 - f)) + 1.5;
+            double lo = floor(pos - del), hi = ceil(pos + del + (pair ? 1.0 : 0.0));
+            if (lo < 0.0) lo = 0.0;
+            if (hi > (double)(S - 1)) hi = (double)(S - 1);
+            const uint32_t rlo = (uint32_t)lo, rhi = (uint32_t)hi;
+            const uint64_t mlo = __ballot(ok && rank == rlo), mhi = __ballot(ok && rank == rhi);
+            const double xv = sh.sval[lane];
+            const double L = lane_bcast(xv, __ffsll((long long)mlo) - 1);
+            const double H = lane_bcast(xv, __ffsll((long long)mhi) - 1);
+            tau = (uint32_t)__double2hiint(fmax(fabs(L), fabs(H)) * 0x1p-6) & 0x7FFFFFFFu;
+            Lk = bin_key<PH>(L, tau);
+            Hk = bin_key<PH>(H, tau);
+        }
+        if (lane == 0) {
+            const uint32_t R = Hk - Lk;
+            const uint32_t nb = 32u - (uint32_t)__clz((int)(R | 1u));
+            sh.Lk = Lk;
+            sh.R = R;
+            sh.sh = nb > 8u ? nb - 8u : 0u;
+            sh.tau = tau;
+            sh.fast = fast0;
+        }
+    }
+    __syncthreads();
+    bool fast = sh.fast != 0;
+    if (fast) {
+        const uint32_t Lk = sh.Lk, R = sh.R, bsh = sh.sh, tau = sh.tau;
+        uint32_t below = 0;
+        const uint32_t dummy = (uint32_t)kBins + (uint32_t)lane;
+        for (int64_t i0 = tid; i0 < n; i0 += (int64_t)kUnroll * kT) {
+            double t[kUnroll];
+#pragma unroll
+            for (int u = 0; u < kUnroll; ++u) {
+                const int64_t i = i0 + (int64_t)u * kT;
+                t[u] = i < n ? col[i] : 0.0;
+            }
+#pragma unroll
+            for (int u = 0; u < kUnroll; ++u) {
+                double x;
+                const bool part = i0 + (int64_t)u * kT < n && phase_val<PH>(t[u], med, x);
+                const uint32_t kx = part ? bin_key<PH>(x, tau) : 0xFFFFFFFFu;
+                const uint32_t dk = kx - Lk;
+                below += (part && kx < Lk) ? 1u : 0u;
+                atomicAdd(&sh.hist[(part && dk <= R) ? (dk >> bsh) : dummy], 1u);
+            }
+        }
+        for (int off = 32; off > 0; off >>= 1) below += (uint32_t)__shfl_xor((int)below, off);
+        if (lane == 0 && below) atomicAdd(&sh.below, below);
+        __syncthreads();
+        if (tid < 64) {
+            const uint64_t base = sh.below;
+            uint32_t bA, rA, cA, bB, rB, cB;
+            bool fA, fB;
+            scan_hist(sh.hist, base, k, bA, rA, cA, fA);
+            scan_hist(sh.hist, base, k + 1, bB, rB, cB, fB);
+            if (fA) {
+                sh.binA = bA;
+                sh.rankA = rA;
+                sh.cntA = cA;
+            }
+            if (fB) {
+                sh.binB = bB;
+                sh.rankB = rB;
+                sh.cntB = cB;
+            }
+            const uint64_t ma = __ballot(fA), mb = __ballot(fB);
+            if (lane == 0) sh.fast = (ma != 0 && (!pair || mb != 0)) ? 1 : 0;
+        }
+        __syncthreads();
+        fast = sh.fast != 0;
+        uint32_t bA = 0, rA = 0, bB = 0, rB = 0;
+        if (fast) {
+            bA = sh.binA;
+            rA = sh.rankA;
+            bB = pair ? sh.binB : bA;
+            rB = pair ? sh.rankB : rA;
+            const bool same = bB == bA;
+            fast = sh.cntA <= (uint32_t)kCapA && (same || sh.cntB <= (uint32_t)kCapB);
+        }
+        if (fast) {
+            for (int64_t i0 = tid; i0 < n; i0 += (int64_t)kUnroll * kT) {
+                double t[kUnroll];
+#pragma unroll
+                for (int u = 0; u < kUnroll; ++u) {
+                    const int64_t i = i0 + (int64_t)u * kT;
+                    t[u] = i < n ? col[i] : 0.0;
+                }
+#pragma unroll
+                for (int u = 0; u < kUnroll; ++u) {
+                    double x;
+                    if (!(i0 + (int64_t)u * kT < n && phase_val<PH>(t[u], med, x))) continue;
+                    const uint32_t dk = bin_key<PH>(x, tau) - Lk;
+                    const uint32_t bx = dk >> bsh;
+                    if (dk <= R && (bx == bA || bx == bB)) {
+                        if (bx == bA) {
+                            const uint32_t p = atomicAdd(&sh.ncandA, 1u);
+                            if (p < (uint32_t)kCapA) sh.candA[p] = x;
+                        } else {
+                            const uint32_t p = atomicAdd(&sh.ncandB, 1u);
+                            if (p < (uint32_t)kCapB) sh.candB[p] = x;
+                        }
+                    }
+                }
+            }
+            __syncthreads();
+            const uint32_t nA = sh.ncandA < (uint32_t)kCapA ? sh.ncandA : (uint32_t)kCapA;
+            const uint32_t nB = sh.ncandB < (uint32_t)kCapB ? sh.ncandB : (uint32_t)kCapB;
+            if ((uint32_t)tid < nA) {
+                const double mine = sh.candA[tid];
+                uint32_t lt = 0, le = 0;
+                for (uint32_t x = 0; x < nA; ++x) {
+                    const double o = sh.candA[x];
+                    lt += (o < mine);
+                    le += (o <= mine);
+                }
+                if (lt <= rA && rA < le) sh.resA = mine;
+                if (pair && bB == bA && lt <= rB && rB < le) sh.resB = mine;
+            }
+            if (pair && bB != bA && (uint32_t)tid < nB) {
+                const double mine = sh.candB[tid];
+                uint32_t lt = 0, le = 0;
+                for (uint32_t x = 0; x < nB; ++x) {
+                    const double o = sh.candB[x];
+                    lt += (o < mine);
+                    le += (o <= mine);
+                }
+                if (lt <= rB && rB < le) sh.resB = mine;
+            }
+            __syncthreads();
+            a = sh.resA;
+            b = pair ? sh.resB : a;
+            __syncthreads();
+            if (stats && tid == 0) atomicAdd(&stats[0], 1u);
+            return;
+        }
+    }
+    __syncthreads();
+    if (stats && tid == 0) atomicAdd(&stats[1], 1u);
+    const uint64_t A = radix_kth_g<PH>(col, n, med, k, sh);
+    a = key_value(A);
+    b = a;
+    if (pair) b = key_value(radix_next_g<PH>(col, n, med, k, A, sh));
+}
+
+template <int PH>
+__device__ double median_stream(const double *__restrict__ col, int64_t n, double med,
+                                uint64_t cnt, RegShared &sh, uint32_t *stats)
+{
+    double a, b;
+    if (cnt & 1) {
+        select_pair_stream<PH>(col, n, med, cnt, cnt / 2, false, a, b, sh, stats);
+        return a;
+    }
+    select_pair_stream<PH>(col, n, med, cnt, cnt / 2 - 1, true, a, b, sh, stats);
+    return (a + b) * 0.5;
+}
+
+template <int NOTION>
+__global__ __launch_bounds__(kT) void k_select_stream(const double *__restrict__ T, int64_t n,
+                                                      int64_t m, int64_t ldm,
+                                                      double *__restrict__ Dj,
+                                                      uint32_t *__restrict__ stats)
+{
+    __shared__ RegShared sh;
+    const int64_t j = blockIdx.x;
+    const int64_t qi = blockIdx.y;
+    const double *col = T + (qi * m + j) * n;
+    const int tid = threadIdx.x;
+    const double med = median_stream<0>(col, n, 0.0, (uint64_t)n, sh, stats);
+    double D;
+    if (NOTION == NOTION_PROJECTION) {
+        const double mad = median_stream<1>(col, n, med, (uint64_t)n, sh, stats);
+        if (mad == 0.0)
+            D = (med == 0.0) ? 1.0 : 0.0;
+        else
+            D = 1.0 / (1.0 + fabs(med) / mad);
+    } else {
+        if (tid == 0) sh.count = 0;
+        __syncthreads();
+        uint32_t np = 0;
+        for (int64_t i = tid; i < n; i += kT) np += (col[i] - med > 0.0) ? 1u : 0u;
+        for (int off = 32; off > 0; off >>= 1) np += (uint32_t)__shfl_xor((int)np, off);
+        if ((tid & 63) == 0 && np) atomicAdd(&sh.count, np);
+        __syncthreads();
+        const uint64_t npos = sh.count;
+        __syncthreads();
+        const double num = (med < 0.0) ? -med : 0.0;
+        if (npos == 0) {
+            D = (num == 0.0) ? 1.0 : 0.0;
+        } else {
+            const double madp = median_stream<2>(col, n, med, npos, sh, stats);
+            D = 1.0 / (1.0 + num / madp);
+        }
+    }
+    if (tid == 0) Dj[qi * ldm + j] = D;
+}
+
 template <int NOTION, int VPT>
 hipError_t launch_vpt(const SelectArgs &a, hipStream_t st)
 {
@@ -574,6 +719,18 @@ hipError_t launch_reg_t(const SelectArgs &a, hipStream_t st)
 }  // namespace
 
 int64_t select_reg_max_n() { return (int64_t)kT * 64; }
+
+hipError_t launch_select_stream(const SelectArgs &a, int notion, hipStream_t st)
+{
+    dim3 grid((unsigned)a.m, (unsigned)a.qb);
+    if (notion == NOTION_PROJECTION)
+        hipLaunchKernelGGL(k_select_stream<NOTION_PROJECTION>, grid, dim3(kT), 0, st, a.T, a.n,
+                           a.m, a.ldm, a.Dj, a.stats);
+    else
+        hipLaunchKernelGGL(k_select_stream<NOTION_APD>, grid, dim3(kT), 0, st, a.T, a.n, a.m,
+                           a.ldm, a.Dj, a.stats);
+    return hipGetLastError();
+}
 
 hipError_t launch_select_reg(const SelectArgs &a, int notion, hipStream_t st)
 {

@@ -1,0 +1,513 @@
+// rrs_select_rc.hip -- step a3 + a4 for projection and asymmetric projection
+// depth from reduced-precision projections, with the order statistics made
+// exact by recomputing only their neighbours in binary64.
+//
+// Input per column (query q, direction j): s_i = a_i.u_j in binary32 from the
+// matrix cores (a_i = x_i - xbar), the centring term c_j (binary64) and a
+// bound E with |(s_i - c_j) - t_i| <= E for every point, where t_i is the
+// recipe's binary64 projection (x_i - z).u_j.  Ranks of s are ranks of s - c.
+//
+// One order statistic of rank k (or the pair k, k + 1):
+//   1. 64 sampled approximations bracket the rank; one pass over the column
+//      counts the approximations below the bracket and bins the rest (as in
+//      the exact selects);
+//   2. the bins holding ranks k, k + 1 span approximations [vlo, vhi], so the
+//      exact statistics lie in [vlo - E, vhi + E] (shifted by c); every point
+//      whose approximation is below vlo - 2E is exactly below them, every one
+//      above vhi + 2E exactly above.  A second pass counts the points below
+//      that window (B) and collects the indices inside it;
+//   3. those candidates are recomputed with the binary64 recipe and ranked
+//      exactly: the statistics are the candidates of ranks k - B, k + 1 - B.
+// MAD (projection depth) is the same select on |s_i - (med + c)| with the
+// exact deviations |t_i - med| for the candidates.  MAD_+ (asymmetric
+// projection depth) needs no deviation phase: the points above the median are
+// the top n - n_le of the order (n_le = #{t <= med}, exact from the median's
+// candidates), so MAD_+ = t_(n_le + k') - med for the middle rank k' of the
+// positive deviations.
+// Anything outside these assumptions (bracket missed, too many candidates)
+// falls back to an exact radix select over recomputed values.  In the plain
+// form (EXACT = false) E = 0 and the candidates take s - c itself, so the
+// result is that of the binary32 projections.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+
+#include "rrs_device.hpp"
+#include "rrs_launch.hpp"
+#include "rrs_select_common.hpp"
+
+namespace rrs {
+
+namespace {
+
+using namespace sel;
+
+constexpr int kT = 256;
+constexpr int kBins = 256;
+constexpr int kCapW = 512;       // candidates of one window
+constexpr int kRadixCand = 64;
+constexpr int kUnroll = 4;
+
+struct RcShared {
+    uint32_t hist[kBins + 64];   // 256 bins, then one dummy slot per lane
+    uint32_t skey[64];
+    uint32_t srank[64];
+    double sval[64];
+    uint32_t cidx[kCapW];
+    double cval[kCapW];
+    uint32_t Lk, R, sh, tau;
+    uint32_t below, ncand;
+    uint32_t binA, binB;
+    int32_t fast;
+    uint32_t count;
+    double resA, resB;
+    uint32_t sel_bucket, sel_before, sel_count;
+    uint64_t rcand[kRadixCand];
+    uint32_t nrcand;
+    uint64_t rresult, minkey;
+};
+
+// One column and what its exact recomputation needs.
+struct Col {
+    const float *s;
+    int64_t n;
+    double c, E;
+    const double *X;   // [n][d]
+    int64_t d;
+    const double *z;   // [d]
+    const double *u;   // direction j: u[c * ldm]
+    int64_t ldm;
+};
+
+// The recipe's projection of point i (EXACT), or the binary32 one shifted.
+template <bool EXACT>
+__device__ __forceinline__ double exact_t(const Col &C, int64_t i)
+{
+    if (!EXACT) return (double)C.s[i] - C.c;
+    const double *x = C.X + i * C.d;
+    double t = 0.0;
+    for (int64_t c = 0; c < C.d; ++c) t = fma(x[c] - C.z[c], C.u[c * C.ldm], t);
+    return t;
+}
+
+// Approximation of point i's value in phase PH (0: s_i; 1: |s_i - sig|).
+template <int PH>
+__device__ __forceinline__ double approx_v(double s, double sig)
+{
+    return PH == 0 ? s : fabs(s - sig);
+}
+
+// Exact value in phase PH from the exact projection t.
+template <int PH>
+__device__ __forceinline__ double exact_v(double t, double med)
+{
+    return PH == 0 ? t : fabs(t - med);
+}
+
+__device__ __forceinline__ double hi_to_double(uint32_t hi) { return __hiloint2double((int)hi, 0); }
+
+// Bounds of the values whose bin_key<PH>(., tau) is K: lo <= x <= hi.
+template <int PH>
+__device__ __forceinline__ double key_lo_value(uint32_t K, uint32_t tau)
+{
+    if (PH == 0) {
+        if (K > 0x80000000u) return hi_to_double(K - 0x80000001u + tau);
+        if (K == 0x80000000u) return -hi_to_double(tau);
+        return -hi_to_double(0x7FFFFFFFu - K + tau + 1u);
+    }
+    return K == 0u ? 0.0 : hi_to_double(K - 1u + tau);
+}
+
+template <int PH>
+__device__ __forceinline__ double key_hi_value(uint32_t K, uint32_t tau)
+{
+    if (PH == 0) {
+        if (K > 0x80000000u) return hi_to_double(K - 0x80000001u + tau + 1u);
+        if (K == 0x80000000u) return hi_to_double(tau);
+        return -hi_to_double(0x7FFFFFFFu - K + tau);
+    }
+    return K == 0u ? hi_to_double(tau) : hi_to_double(K + tau);
+}
+
+// Exact radix select (rank k) over the recomputed values of phase PH.
+template <int PH, bool EXACT>
+__device__ uint64_t rc_radix_kth(const Col &C, double med, uint64_t k, RcShared &sh)
+{
+    const int tid = threadIdx.x, lane = tid & 63;
+    uint64_t prefix = 0, pmask = 0;
+    for (int shift = 56; shift >= 0; shift -= 8) {
+        sh.hist[tid] = 0;
+        __syncthreads();
+        for (int64_t i = tid; i < C.n; i += kT) {
+            const uint64_t key = order_key(exact_v<PH>(exact_t<EXACT>(C, i), med));
+            if ((key & pmask) == prefix) atomicAdd(&sh.hist[(uint32_t)(key >> shift) & 255u], 1u);
+        }
+        __syncthreads();
+        if (tid < 64) {
+            uint32_t bin, rin, cnt;
+            bool found;
+            scan_hist(sh.hist, 0, k, bin, rin, cnt, found);
+            if (found) {
+                sh.sel_bucket = bin;
+                sh.sel_before = (uint32_t)(k - rin);
+                sh.sel_count = cnt;
+            }
+        }
+        __syncthreads();
+        const uint32_t selb = sh.sel_bucket, cntb = sh.sel_count;
+        k -= sh.sel_before;
+        prefix |= (uint64_t)selb << shift;
+        pmask |= 0xFFull << shift;
+        if (shift == 0) break;
+        if (cntb <= (uint32_t)kRadixCand) {
+            if (tid == 0) sh.nrcand = 0;
+            __syncthreads();
+            for (int64_t i = tid; i < C.n; i += kT) {
+                const uint64_t key = order_key(exact_v<PH>(exact_t<EXACT>(C, i), med));
+                if ((key & pmask) == prefix) {
+                    const uint32_t pos = atomicAdd(&sh.nrcand, 1u);
+                    if (pos < (uint32_t)kRadixCand) sh.rcand[pos] = key;
+                }
+            }
+            __syncthreads();
+            if (tid < 64) {
+                const uint32_t nc = sh.nrcand < (uint32_t)kRadixCand ? sh.nrcand
+                                                                     : (uint32_t)kRadixCand;
+                if ((uint32_t)lane < nc) {
+                    const uint64_t mine = sh.rcand[lane];
+                    uint32_t lt = 0, le = 0;
+                    for (uint32_t x = 0; x < nc; ++x) {
+                        const uint64_t o = sh.rcand[x];
+                        lt += (o < mine);
+                        le += (o <= mine);
+                    }
+                    if (lt <= k && k < le) sh.rresult = mine;
+                }
+            }
+            __syncthreads();
+            const uint64_t r = sh.rresult;
+            __syncthreads();
+            return r;
+        }
+    }
+    __syncthreads();
+    return prefix;
+}
+
+// Key of the (k+1)-th smallest given the key A of the k-th (exact values).
+template <int PH, bool EXACT>
+__device__ uint64_t rc_radix_next(const Col &C, double med, uint64_t k, uint64_t A,
+                                  RcShared &sh)
+{
+    const int tid = threadIdx.x;
+    if (tid == 0) {
+        sh.count = 0;
+        sh.minkey = ~0ull;
+    }
+    __syncthreads();
+    uint32_t le = 0;
+    uint64_t mn = ~0ull;
+    for (int64_t i = tid; i < C.n; i += kT) {
+        const uint64_t key = order_key(exact_v<PH>(exact_t<EXACT>(C, i), med));
+        le += (key <= A);
+        if (key > A && key < mn) mn = key;
+    }
+    if (le) atomicAdd(&sh.count, le);
+    if (mn != ~0ull) atomicMin((unsigned long long *)&sh.minkey, (unsigned long long)mn);
+    __syncthreads();
+    const uint64_t res = ((uint64_t)sh.count >= k + 2) ? A : sh.minkey;
+    __syncthreads();
+    return res;
+}
+
+// The exact values of ranks k (and k + 1 if pair) in phase PH.  Returns true
+// when the window path served them; then sh.cval[0 .. ncand) holds the
+// window's exact values and *below the number of points under the window.
+template <int PH, bool EXACT>
+__device__ bool rc_select(const Col &C, double med, double sig, double E, uint64_t k, bool pair,
+                          double &a, double &b, uint64_t *below, RcShared &sh, uint32_t *stats)
+{
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int64_t n = C.n;
+    sh.hist[tid] = 0;
+    if (tid < 64) sh.srank[tid] = 0;
+    if (tid == 0) {
+        sh.below = 0;
+        sh.ncand = 0;
+    }
+    if (tid < 64) {
+        const int64_t i = ((2 * (int64_t)tid + 1) * n) / 128;
+        const double x = approx_v<PH>((double)C.s[i], sig);
+        const uint32_t kx = key32<PH>(x);
+        sh.skey[tid] = key_takes_part<PH>(kx) ? kx : 0xFFFFFFFFu;
+        sh.sval[tid] = x;
+    }
+    __syncthreads();
+    {
+        const uint32_t mine = sh.skey[lane];
+        uint32_t part = 0;
+#pragma unroll
+        for (int jj = 0; jj < 16; ++jj) {
+            const int o = wave * 16 + jj;
+            const uint32_t ko = sh.skey[o];
+            part += (ko < mine || (ko == mine && o < lane)) ? 1u : 0u;
+        }
+        atomicAdd(&sh.srank[lane], part);
+    }
+    __syncthreads();
+    if (tid < 64) {
+        const uint32_t kx = sh.skey[lane];
+        const bool ok = kx != 0xFFFFFFFFu;
+        const uint32_t rank = sh.srank[lane];
+        const uint32_t S = (uint32_t)__popcll(__ballot(ok));
+        int fast0 = S >= 16 ? 1 : 0;
+        uint32_t Lk = 0, Hk = 0, tau = 0;
+        if (fast0) {
+            const double f = ((double)k + 0.5) / (double)n;
+            const double pos = f * (double)S;
+            const double del = 2.5 * sqrt((double)S * f * (1.0 - f)) + 1.5;
+            double lo = floor(pos - del), hi = ceil(pos + del + (pair ? 1.0 : 0.0));
+            if (lo < 0.0) lo = 0.0;
+            if (hi > (double)(S - 1)) hi = (double)(S - 1);
+            const uint32_t rlo = (uint32_t)lo, rhi = (uint32_t)hi;
+            const uint64_t mlo = __ballot(ok && rank == rlo), mhi = __ballot(ok && rank == rhi);
+            const double xv = sh.sval[lane];
+            const double L = lane_bcast(xv, __ffsll((long long)mlo) - 1);
+            const double H = lane_bcast(xv, __ffsll((long long)mhi) - 1);
+            tau = (uint32_t)__double2hiint(fmax(fabs(L), fabs(H)) * 0x1p-6) & 0x7FFFFFFFu;
+            Lk = bin_key<PH>(L, tau);
+            Hk = bin_key<PH>(H, tau);
+        }
+        if (lane == 0) {
+            const uint32_t R = Hk - Lk;
+            const uint32_t nb = 32u - (uint32_t)__clz((int)(R | 1u));
+            sh.Lk = Lk;
+            sh.R = R;
+            sh.sh = nb > 8u ? nb - 8u : 0u;
+            sh.tau = tau;
+            sh.fast = fast0;
+        }
+    }
+    __syncthreads();
+    bool fast = sh.fast != 0;
+    if (fast) {
+        const uint32_t Lk = sh.Lk, R = sh.R, bsh = sh.sh, tau = sh.tau;
+        uint32_t nbelow = 0;
+        const uint32_t dummy = (uint32_t)kBins + (uint32_t)lane;
+        for (int64_t i0 = tid; i0 < n; i0 += (int64_t)kUnroll * kT) {
+            float t[kUnroll];
+#pragma unroll
+            for (int u = 0; u < kUnroll; ++u) {
+                const int64_t i = i0 + (int64_t)u * kT;
+                t[u] = i < n ? C.s[i] : 0.0f;
+            }
+#pragma unroll
+            for (int u = 0; u < kUnroll; ++u) {
+                const bool live = i0 + (int64_t)u * kT < n;
+                const uint32_t kx = bin_key<PH>(approx_v<PH>((double)t[u], sig), tau);
+                const uint32_t dk = kx - Lk;
+                nbelow += (live && kx < Lk) ? 1u : 0u;
+                atomicAdd(&sh.hist[(live && dk <= R) ? (dk >> bsh) : dummy], 1u);
+            }
+        }
+        for (int off = 32; off > 0; off >>= 1) nbelow += (uint32_t)__shfl_xor((int)nbelow, off);
+        if (lane == 0 && nbelow) atomicAdd(&sh.below, nbelow);
+        __syncthreads();
+        if (tid < 64) {
+            const uint64_t base = sh.below;
+            uint32_t bA, rA, cA, bB, rB, cB;
+            bool fA, fB;
+            scan_hist(sh.hist, base, k, bA, rA, cA, fA);
+            scan_hist(sh.hist, base, k + 1, bB, rB, cB, fB);
+            if (fA) sh.binA = bA;
+            if (fB) sh.binB = bB;
+            const uint64_t ma = __ballot(fA), mb = __ballot(fB);
+            if (lane == 0) sh.fast = (ma != 0 && (!pair || mb != 0)) ? 1 : 0;
+        }
+        __syncthreads();
+        fast = sh.fast != 0;
+        if (fast) {
+            const uint32_t bA = sh.binA, bB = pair ? sh.binB : sh.binA;
+            // approximations of the target bins lie in [vlo, vhi]
+            const uint64_t klo = (uint64_t)Lk + ((uint64_t)bA << bsh);
+            uint64_t khi = (uint64_t)Lk + (((uint64_t)bB + 1) << bsh) - 1;
+            if (khi > (uint64_t)Lk + R) khi = (uint64_t)Lk + R;
+            const double vlo = key_lo_value<PH>((uint32_t)klo, tau);
+            const double vhi = key_hi_value<PH>((uint32_t)khi, tau);
+            // phase 1 adds the rounding of s - sig (binary64) to the bound
+            const double Ew = PH == 0 ? E : E * 1.000001 + 0x1p-48 * (fabs(sig) + fabs(vlo) +
+                                                                      fabs(vhi) + E);
+            const double wlo = vlo - 2.0 * Ew, whi = vhi + 2.0 * Ew;
+            if (tid == 0) sh.below = 0;
+            __syncthreads();
+            nbelow = 0;
+            for (int64_t i0 = tid; i0 < n; i0 += (int64_t)kUnroll * kT) {
+                float t[kUnroll];
+#pragma unroll
+                for (int u = 0; u < kUnroll; ++u) {
+                    const int64_t i = i0 + (int64_t)u * kT;
+                    t[u] = i < n ? C.s[i] : 0.0f;
+                }
+#pragma unroll
+                for (int u = 0; u < kUnroll; ++u) {
+                    const int64_t i = i0 + (int64_t)u * kT;
+                    if (i >= n) continue;
+                    const double x = approx_v<PH>((double)t[u], sig);
+                    nbelow += (x < wlo) ? 1u : 0u;
+                    if (x >= wlo && x <= whi) {
+                        const uint32_t p = atomicAdd(&sh.ncand, 1u);
+                        if (p < (uint32_t)kCapW) sh.cidx[p] = (uint32_t)i;
+                    }
+                }
+            }
+            for (int off = 32; off > 0; off >>= 1)
+                nbelow += (uint32_t)__shfl_xor((int)nbelow, off);
+            if (lane == 0 && nbelow) atomicAdd(&sh.below, nbelow);
+            __syncthreads();
+            const uint32_t nc = sh.ncand;
+            const uint64_t B = sh.below;
+            fast = nc <= (uint32_t)kCapW && B <= k && k + (pair ? 1 : 0) < B + nc;
+            if (fast) {
+                for (uint32_t p = tid; p < nc; p += kT)
+                    sh.cval[p] = exact_v<PH>(exact_t<EXACT>(C, (int64_t)sh.cidx[p]), med);
+                __syncthreads();
+                const uint64_t rA = k - B, rB = k + 1 - B;
+                for (uint32_t p = tid; p < nc; p += kT) {
+                    const double mine = sh.cval[p];
+                    uint32_t lt = 0, le = 0;
+                    for (uint32_t x = 0; x < nc; ++x) {
+                        const double o = sh.cval[x];
+                        lt += (o < mine);
+                        le += (o <= mine);
+                    }
+                    if (lt <= rA && rA < le) sh.resA = mine;
+                    if (pair && lt <= rB && rB < le) sh.resB = mine;
+                }
+                __syncthreads();
+                a = sh.resA;
+                b = pair ? sh.resB : a;
+                *below = B;
+                if (stats && tid == 0) atomicAdd(&stats[0], 1u);
+                return true;
+            }
+        }
+    }
+    __syncthreads();
+    if (stats && tid == 0) atomicAdd(&stats[1], 1u);
+    const uint64_t A = rc_radix_kth<PH, EXACT>(C, med, k, sh);
+    a = key_value(A);
+    b = a;
+    if (pair) b = key_value(rc_radix_next<PH, EXACT>(C, med, k, A, sh));
+    return false;
+}
+
+// Number of points with t <= med: from the median's window when it served,
+// else by a counting pass over recomputed values.
+template <bool EXACT>
+__device__ uint64_t rc_count_le(const Col &C, double med, bool window, uint64_t below,
+                                RcShared &sh)
+{
+    const int tid = threadIdx.x, lane = tid & 63;
+    if (tid == 0) sh.count = 0;
+    __syncthreads();
+    uint32_t c = 0;
+    if (window) {
+        const uint32_t nc = sh.ncand;
+        for (uint32_t p = tid; p < nc; p += kT) c += sh.cval[p] <= med ? 1u : 0u;
+    } else {
+        for (int64_t i = tid; i < C.n; i += kT) c += exact_t<EXACT>(C, i) <= med ? 1u : 0u;
+    }
+    for (int off = 32; off > 0; off >>= 1) c += (uint32_t)__shfl_xor((int)c, off);
+    if (lane == 0 && c) atomicAdd(&sh.count, c);
+    __syncthreads();
+    const uint64_t r = (window ? below : 0) + sh.count;
+    __syncthreads();
+    return r;
+}
+
+template <int NOTION, bool EXACT>
+__global__ __launch_bounds__(kT) void k_select_rc(const float *__restrict__ S, int64_t n,
+                                                  int64_t m, int64_t ldm, int64_t ldb,
+                                                  const double *__restrict__ cq,
+                                                  const double *__restrict__ eq,
+                                                  const double *__restrict__ X, int64_t d,
+                                                  const double *__restrict__ Zb,
+                                                  const double *__restrict__ UT,
+                                                  double *__restrict__ Dj,
+                                                  uint32_t *__restrict__ stats)
+{
+    __shared__ RcShared sh;
+    const int64_t j = blockIdx.x;
+    const int64_t qi = blockIdx.y;
+    Col C;
+    C.s = S + (qi * m + j) * n;
+    C.n = n;
+    C.c = cq[qi * ldb + j];
+    C.E = EXACT ? eq[qi * ldb + j] : 0.0;
+    C.X = X;
+    C.d = d;
+    C.z = Zb + qi * d;
+    C.u = UT + qi * d * ldm + j;
+    C.ldm = ldm;
+    // rank k of the s values is rank k of the s - c values: the windows live
+    // in s space (|(s - c) - t| <= E moves every statistic by at most E, and
+    // c is common to the column), the candidates' exact values in t space
+    const bool odd = (n & 1) != 0;
+    const uint64_t k = odd ? (uint64_t)n / 2 : (uint64_t)n / 2 - 1;
+    double a, b;
+    uint64_t below = 0;
+    const bool win = rc_select<0, EXACT>(C, 0.0, 0.0, C.E, k, !odd, a, b, &below, sh, stats);
+    const double med = odd ? a : (a + b) * 0.5;
+    double D;
+    if (NOTION == NOTION_PROJECTION) {
+        double m1, m2;
+        uint64_t b1 = 0;
+        rc_select<1, EXACT>(C, med, med + C.c, C.E, k, !odd, m1, m2, &b1, sh, stats);
+        const double mad = odd ? m1 : (m1 + m2) * 0.5;
+        if (mad == 0.0)
+            D = (med == 0.0) ? 1.0 : 0.0;
+        else
+            D = 1.0 / (1.0 + fabs(med) / mad);
+    } else {
+        const uint64_t nle = rc_count_le<EXACT>(C, med, win, below, sh);
+        const uint64_t npos = (uint64_t)n - nle;
+        const double num = (med < 0.0) ? -med : 0.0;
+        if (npos == 0) {
+            D = (num == 0.0) ? 1.0 : 0.0;
+        } else {
+            const bool podd = (npos & 1) != 0;
+            const uint64_t kp = nle + (podd ? npos / 2 : npos / 2 - 1);
+            double p1, p2;
+            uint64_t b2 = 0;
+            rc_select<0, EXACT>(C, 0.0, 0.0, C.E, kp, !podd, p1, p2, &b2, sh, stats);
+            const double madp = podd ? (p1 - med) : ((p1 - med) + (p2 - med)) * 0.5;
+            D = 1.0 / (1.0 + num / madp);
+        }
+    }
+    if (threadIdx.x == 0) Dj[qi * ldm + j] = D;
+}
+
+}  // namespace
+
+hipError_t launch_select_rc(const SelectRcArgs &a, int notion, bool exact, hipStream_t st)
+{
+    dim3 grid((unsigned)a.m, (unsigned)a.qb);
+#define RRS_SEL(N, E)                                                                         \
+    hipLaunchKernelGGL((k_select_rc<N, E>), grid, dim3(kT), 0, st, a.S, a.n, a.m, a.ldm, a.ldb, \
+                       a.cq, a.eq, a.X, a.d, a.Z, a.UT, a.Dj, a.stats)
+    if (notion == NOTION_PROJECTION) {
+        if (exact)
+            RRS_SEL(NOTION_PROJECTION, true);
+        else
+            RRS_SEL(NOTION_PROJECTION, false);
+    } else {
+        if (exact)
+            RRS_SEL(NOTION_APD, true);
+        else
+            RRS_SEL(NOTION_APD, false);
+    }
+#undef RRS_SEL
+    return hipGetLastError();
+}
+
+}  // namespace rrs

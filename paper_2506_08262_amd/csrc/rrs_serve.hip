@@ -116,6 +116,7 @@ struct rrs_dataset {
         double *xbar = nullptr;
         void *A0 = nullptr, *A1 = nullptr;
         float *anorm = nullptr;
+        float *amax = nullptr;
         hipEvent_t ready = nullptr;
     } ops[3];
     int refs = 0;               // requests submitted and not finished
@@ -241,8 +242,9 @@ rrs_status launch_request(rrs_ctx *c, rrs_request *r, int slot, bool prep_ops)
             o.A1 = rrs::mfma_terms(prec) == 2 ? (void *)oc.take<char>((size_t)ds->n * kp * eb)
                                                : nullptr;
             o.anorm = oc.take<float>((size_t)ds->n);
+            o.amax = oc.take<float>(16);
             RRS_HIP_TRY(rrs::launch_mfma_prep(prec, ds->base.X, ds->n, d, o.xbar, o.A0, o.A1,
-                                              o.anorm, st));
+                                              o.anorm, o.amax, st));
             RRS_HIP_TRY(hipEventCreateWithFlags(&o.ready, hipEventDisableTiming));
             RRS_HIP_TRY(hipEventRecord(o.ready, st));
         } else {
@@ -253,6 +255,7 @@ rrs_status launch_request(rrs_ctx *c, rrs_request *r, int slot, bool prep_ops)
         D.A0 = o.A0;
         D.A1 = o.A1;
         D.anorm = o.anorm;
+        D.amax = o.amax;
     }
     rrs::JobIO io;
     io.Z = Zd;

@@ -21,6 +21,11 @@ configurations (all synthetic, as in the paper's own experiments):
 * ``c5``  halfspace / projection, X 100000x100 from a 3-component Gaussian
           mixture (means N(0,I), covariances Wishart(d,I)/d), 500 queries,
           K=5000, r=25, alpha=0.6.
+* ``c4``  serving stream (``c4_stream``): Poisson arrivals at 200 requests/s,
+          halfspace or projection (1/2 each), each request with its own data
+          set: n log-uniform in [1e3, 1e5], d uniform in {3..100}, N(0,I) or
+          multivariate t(3) (1/2 each), 1..1000 queries of the same law,
+          K in {1000, 5000, 10000}, r=10, alpha=0.5; seed_cfg 5.
 * ``toeplitz`` the paper's experimental law N(0, T), T_ij = 2^-|i-j|.
 
 ``seed_cfg`` seeds numpy; the RRS direction stream is keyed separately by
@@ -33,7 +38,8 @@ from dataclasses import dataclass, field
 import numpy as np
 
 __all__ = ["Workload", "make", "gaussian", "toeplitz_gaussian", "wishart_gaussian",
-           "rotated_exponential", "gaussian_mixture", "student_t", "WORKLOADS"]
+           "rotated_exponential", "gaussian_mixture", "student_t", "WORKLOADS", "c4_stream",
+           "ServingRequest"]
 
 
 @dataclass
@@ -216,3 +222,47 @@ def small(notion: str, n: int, d: int, nq: int, K: int, n_refine: int, cap_shrin
     return Workload(f"small-{law}", notion, np.ascontiguousarray(X), np.ascontiguousarray(Z),
                     K, n_refine, cap_shrink, rrs_seed,
                     f"{law} n={n} d={d} nq={nq} seed_cfg={seed_cfg}")
+
+
+@dataclass
+class ServingRequest:
+    """One request of the serving stream: arrival time (s from the stream's
+    start), its own data set and queries, and the RRS arguments."""
+    arrival: float
+    notion: str
+    X: np.ndarray
+    Z: np.ndarray
+    K: int
+    n_refine: int
+    cap_shrink: float
+    law: str
+
+    @property
+    def projections(self) -> int:
+        m = -(-self.K // self.n_refine)
+        return self.Z.shape[0] * self.n_refine * m * self.X.shape[0]
+
+
+def c4_stream(n_requests: int, rate: float = 200.0, seed_cfg: int = 5,
+              max_queries: int = 1000):
+    """The first n_requests requests of the serving stream (see the module
+    notes); max_queries caps the per-request query count below 1000 when a
+    shorter run is wanted (the law of the other fields is unchanged)."""
+    rng = np.random.default_rng(seed_cfg)
+    t = 0.0
+    out = []
+    for _ in range(n_requests):
+        t += rng.exponential(1.0 / rate)
+        notion = "halfspace" if rng.random() < 0.5 else "projection"
+        n = int(np.floor(10.0 ** rng.uniform(3.0, 5.0)))
+        d = int(rng.integers(3, 101))
+        law = "gaussian" if rng.random() < 0.5 else "t3"
+        nq = int(rng.integers(1, min(1000, max_queries) + 1))
+        K = int(rng.choice([1000, 5000, 10000]))
+        if law == "gaussian":
+            X, Z = gaussian(rng, n, d), gaussian(rng, nq, d)
+        else:
+            X, Z = student_t(rng, n, d, 3), student_t(rng, nq, d, 3)
+        out.append(ServingRequest(t, notion, np.ascontiguousarray(X), np.ascontiguousarray(Z),
+                                  K, 10, 0.5, law))
+    return out

@@ -127,9 +127,12 @@ def test_ties_and_points_equal_to_queries(notion):
 
 
 @pytest.mark.parametrize("notion", ["projection", "apd"])
-def test_select_from_global_memory(notion):
-    # n beyond the LDS-resident column size: the select streams from HBM
-    w = workloads.small(notion, 24001, 3, 3, 32, 2, 0.5, law="gaussian", seed_cfg=5)
+@pytest.mark.parametrize("n,law", [(16385, "gaussian"), (24001, "gaussian"),
+                                   (40000, "integer"), (33333, "exponential")])
+def test_select_streaming_long_columns(notion, n, law):
+    # columns longer than the register-resident select holds: the streaming
+    # select re-reads them from global memory
+    w = workloads.small(notion, n, 3, 3, 32, 2, 0.5, law=law, seed_cfg=5 + n % 7)
     _compare(notion, w)
 
 
@@ -256,11 +259,66 @@ def test_f32_plain_halfspace_error_is_reported_and_small():
     assert np.abs(p1 - e1).max() <= 2
 
 
-@pytest.mark.parametrize("prec", ["bf16", "f32", "f32_plain"])
-def test_mfma_forms_rejected_for_projection(prec):
-    w = workloads.small("projection", 100, 3, 2, 20, 2, 0.5)
-    with pytest.raises(rrs.RRSError):
-        rrs.rrs_depth_projection(w.X, w.Z, w.K, w.n_refine, w.cap_shrink, precision=prec)
+# --------------------------------------------------------------------------
+# Projection / APD depth from matrix-core projections (binary32 s = a.u):
+# the order statistics are made exact by recomputing their window in
+# binary64, so depths, poles and traces are identical to the binary64 form.
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("prec", MFMA_EXACT)
+@pytest.mark.parametrize("notion", ["projection", "apd"])
+@pytest.mark.parametrize("n,d,law", [(1000, 5, "gaussian"), (777, 7, "exponential"),
+                                     (1200, 20, "wishart_cauchy"), (901, 3, "integer"),
+                                     (640, 100, "mixture")])
+def test_mfma_depth_parity(prec, notion, n, d, law):
+    w = workloads.small(notion, n, d, 12, 240, 6, 0.5, law=law, seed_cfg=n + d)
+    _compare(notion, w, precision=prec)
+
+
+@pytest.mark.parametrize("prec", MFMA_EXACT)
+@pytest.mark.parametrize("notion", ["projection", "apd"])
+@pytest.mark.parametrize("n", [1, 2, 3, 4, 63, 513, 20001])
+def test_mfma_depth_tiny_ragged_and_long(prec, notion, n):
+    w = workloads.small(notion, n, 4, 5, 60, 3, 0.5, law="gaussian", seed_cfg=n + 17)
+    _compare(notion, w, precision=prec)
+
+
+@pytest.mark.parametrize("prec", MFMA_EXACT)
+@pytest.mark.parametrize("notion", ["projection", "apd"])
+def test_mfma_depth_ties_offsets_and_far_queries(prec, notion):
+    w = workloads.small(notion, 500, 4, 16, 160, 4, 0.5, law="integer", seed_cfg=79)
+    Z = w.Z.copy()
+    Z[:6] = w.X[:6]
+    Z[6] = 1e4
+    w.Z = Z
+    X = w.X.copy()
+    X[100:180] = X[0]
+    w.X = X
+    _compare(notion, w, precision=prec)
+    w2 = workloads.small(notion, 900, 6, 8, 120, 4, 0.6, law="gaussian", seed_cfg=80)
+    w2.X = w2.X + 1e3
+    w2.Z = w2.Z + 1e3
+    _compare(notion, w2, precision=prec)
+
+
+@pytest.mark.parametrize("notion", ["projection", "apd"])
+def test_f32_plain_depth_error_is_reported_and_small(notion):
+    """Plain binary32 projections, no recheck: with one refinement (the same
+    sphere directions in both forms) every depth is within a small relative
+    error of the binary64 one; the full trajectory may differ and its error
+    is reported."""
+    w = workloads.make("c1")
+    one = rrs.depth(notion, w.X, w.Z, 300, 1, 1.0, 2)["depth"]
+    p1 = rrs.depth(notion, w.X, w.Z, 300, 1, 1.0, 2, precision="f32_plain")["depth"]
+    rel = np.abs(p1 - one) / np.maximum(np.abs(one), 1e-300)
+    _say(notion, "f32_plain single-refinement max rel err", float(rel.max()))
+    assert rel.max() <= 1e-5
+    full = rrs.depth(notion, w.X, w.Z, w.K, w.n_refine, w.cap_shrink, 0)["depth"]
+    pf = rrs.depth(notion, w.X, w.Z, w.K, w.n_refine, w.cap_shrink, 0,
+                   precision="f32_plain")["depth"]
+    relf = np.abs(pf - full) / np.maximum(np.abs(full), 1e-300)
+    _say(notion, "f32_plain full RRS: max rel err", float(relf.max()), "mean",
+         float(relf.mean()), "exact queries", int((relf == 0).sum()), "of", len(relf))
+    assert relf.max() <= 1e-2
 
 
 def test_select_fast_path_dominates_on_centred_columns():
