@@ -198,14 +198,15 @@ int job_sizes(const JobSpec &s, int64_t n, int64_t d, const Plan &p, int64_t qb,
     sz[k++] = (half || mfma) ? 0 : (size_t)qb * p.m * n * 8;    // T (binary64)
     sz[k++] = half ? 0 : (size_t)qb * p.ldm * 8;                // Dj
     sz[k++] = 64;                                               // stats
-    sz[k++] = mfma ? (size_t)qb * p.ldb * p.kp * p.eb : 0;      // B0
-    sz[k++] = (mfma && p.terms == 2) ? (size_t)qb * p.ldb * p.kp * p.eb : 0;  // B1
-    sz[k++] = (mfma && half) ? (size_t)qb * p.ldb * 4 : 0;      // cmarg
+    const size_t npad = mfma ? (size_t)mfma_col_pad(qb * p.m) : 0;
+    sz[k++] = mfma ? npad * p.kp * p.eb : 0;                    // B0
+    sz[k++] = (mfma && p.terms == 2) ? npad * p.kp * p.eb : 0;  // B1
+    sz[k++] = (mfma && half) ? npad * 4 : 0;                    // cmarg
     sz[k++] = (mfma && half) ? (size_t)p.qcap * 8 : 0;          // queue
     sz[k++] = 64;                                               // qctl
     sz[k++] = (mfma && !half) ? (size_t)qb * p.m * n * 4 : 0;   // S (binary32)
-    sz[k++] = (mfma && !half) ? (size_t)qb * p.ldb * 8 : 0;     // cq
-    sz[k++] = (mfma && !half) ? (size_t)qb * p.ldb * 8 : 0;     // eq
+    sz[k++] = (mfma && !half) ? npad * 8 : 0;                   // cq
+    sz[k++] = (mfma && !half) ? npad * 8 : 0;                   // eq
     return k;
 }
 
@@ -226,7 +227,7 @@ rrs_status job_plan(const JobSpec &s, int64_t n, int64_t d, size_t limit, Plan *
     p.prec = job_mfma_prec(s.precision);
     p.m = (s.K + s.r - 1) / s.r;
     p.ldm = (p.m + kProjJT - 1) / kProjJT * kProjJT;
-    p.ldb = (p.m + kMfmaCols - 1) / kMfmaCols * kMfmaCols;
+
     if (p.prec >= 0) {
         p.kp = mfma_kpad(p.prec, d);
         p.eb = mfma_elem_bytes(p.prec);
@@ -262,7 +263,8 @@ rrs_status job_plan(const JobSpec &s, int64_t n, int64_t d, size_t limit, Plan *
 rrs_status enqueue_job(const JobSpec &s, const DataDev &D, const Plan &p, const JobIO &io,
                        void *ws, hipStream_t st, Profiler *prof, uint32_t **stats_out)
 {
-    const int64_t n = D.n, d = D.d, nq = s.nq, m = p.m, ldm = p.ldm, ldb = p.ldb, qb = p.qb;
+    const int64_t n = D.n, d = D.d, nq = s.nq, m = p.m, ldm = p.ldm, qb = p.qb;
+    const int64_t npad = p.prec >= 0 ? mfma_col_pad(qb * m) : 0;
     const int32_t r = s.r;
     const bool half = s.notion == NOTION_HALFSPACE;
     const bool mfma = p.prec >= 0;
@@ -309,10 +311,10 @@ rrs_status enqueue_job(const JobSpec &s, const DataDev &D, const Plan &p, const 
             if (half && mfma) {
                 RRS_HIP_TRY(launch_fill_u32(cnt, nb * ldm * 2, 0u, st));
                 RRS_HIP_TRY(launch_fill_u32(qctl, 16, 0u, st));
-                RRS_HIP_TRY(launch_mfma_dirs(p.prec, true, UT, d, m, ldm, ldb, nb, Zb, D.xbar, B0,
-                                             B1, cmarg, D.amax, nullptr, nullptr, st));
+                RRS_HIP_TRY(launch_mfma_dirs(p.prec, true, UT, d, m, ldm, nb * m, npad, Zb, D.xbar,
+                                             B0, B1, cmarg, D.amax, nullptr, nullptr, st));
                 MfmaArgs ma{p.prec, D.A0,   D.A1,   D.anorm, n,    d,    B0,
-                            B1,     cmarg,  m,      ldm,     ldb,  nb,   cnt,
+                            B1,     cmarg,  m,      ldm,     npad, nb,   cnt,
                             queue,  qctl,   p.qcap, qctl + 1, D.X, Zb,   UT,
                             profiling ? (uint64_t *)(stats + 4) : nullptr};
                 {
@@ -330,14 +332,14 @@ rrs_status enqueue_job(const JobSpec &s, const DataDev &D, const Plan &p, const 
                 }
             } else if (mfma) {
                 // projection / APD from binary32 projections on the matrix cores
-                RRS_HIP_TRY(launch_mfma_dirs(p.prec, false, UT, d, m, ldm, ldb, nb, Zb, D.xbar,
-                                             B0, B1, nullptr, D.amax, cq, eq, st));
+                RRS_HIP_TRY(launch_mfma_dirs(p.prec, false, UT, d, m, ldm, nb * m, npad, Zb,
+                                             D.xbar, B0, B1, nullptr, D.amax, cq, eq, st));
                 {
                     ProfScope ps(prof, K_MFMA, proj_units, st);
-                    RRS_HIP_TRY(launch_mfma_store(p.prec, D.A0, D.A1, n, d, B0, B1, m, ldb, nb,
-                                                  S32, st));
+                    RRS_HIP_TRY(launch_mfma_store(p.prec, D.A0, D.A1, n, d, B0, B1, m, nb * m,
+                                                  npad, S32, st));
                 }
-                SelectRcArgs ra{S32, n,  m,  ldm, ldb, nb, cq, eq, D.X, d, Zb, UT, Dj,
+                SelectRcArgs ra{S32, n, m, ldm, nb, cq, eq, D.X, d, Zb, UT, Dj,
                                 profiling ? stats : nullptr};
                 ProfScope ps(prof, K_SELECT, proj_units, st);
                 RRS_HIP_TRY(launch_select_rc(ra, s.notion, p.prec != MFMA_F32_PLAIN, st));

@@ -109,7 +109,7 @@ rrs_status job_validate(const JobSpec &s, int64_t n, int64_t d);
 int job_mfma_prec(int precision);
 
 struct Plan {
-    int64_t m = 0, ldm = 0, ldb = 0, kp = 0, qb = 0;
+    int64_t m = 0, ldm = 0, kp = 0, qb = 0;
     size_t eb = 0;
     int terms = 0, prec = -1;
     uint64_t qcap = 0;

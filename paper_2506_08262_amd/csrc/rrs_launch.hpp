@@ -38,9 +38,9 @@ struct MfmaArgs {
     const void *A0, *A1;       // [n][kp] centred data: bf16 hi/lo, or binary32 in A0
     const float *anorm;        // [n] norm bound of the centred points
     int64_t n, d;
-    const void *B0, *B1;       // [qb][ldb][kp] directions + centring, same format
-    const float *cmarg;        // [qb][ldb] direction part of the margin
-    int64_t m, ldm, ldb, qb;
+    const void *B0, *B1;       // [npad][kp] directions + centring (flat columns q m + j)
+    const float *cmarg;        // [npad] direction part of the margin
+    int64_t m, ldm, npad, qb;
     uint32_t *cnt;             // [qb][ldm][2]
     uint64_t *queue;           // uncertain (query, direction, point)
     uint32_t *qcount;
@@ -62,8 +62,8 @@ struct SelectArgs {
 // Projection / APD depth from binary32 projections (rrs_select_rc.hip).
 struct SelectRcArgs {
     const float *S;            // [qb][m][n] s_ij = a_i.u_j
-    int64_t n, m, ldm, ldb, qb;
-    const double *cq, *eq;     // [qb][ldb] centring terms and error bounds
+    int64_t n, m, ldm, qb;
+    const double *cq, *eq;     // [qb m] centring terms and error bounds (flat columns)
     const double *X;           // [n][d] binary64 data (recompute)
     int64_t d;
     const double *Z;           // [qb][d]
@@ -103,15 +103,15 @@ void mfma_margins(int prec, int64_t d, int64_t kp, double *kappa, double *canon)
 hipError_t launch_mfma_prep(int prec, const double *X, int64_t n, int64_t d, double *xbar,
                             void *A0, void *A1, float *anorm, float *amax, hipStream_t st);
 hipError_t launch_mfma_dirs(int prec, bool fold, const double *UT, int64_t d, int64_t m,
-                            int64_t ldm, int64_t ldb, int64_t qb, const double *Zb,
+                            int64_t ldm, int64_t ncols, int64_t npad, const double *Zb,
                             const double *xbar, void *B0, void *B1, float *cmarg,
                             const float *amax, double *cq, double *eq, hipStream_t st);
 hipError_t launch_mfma_store(int prec, const void *A0, const void *A1, int64_t n, int64_t d,
-                             const void *B0, const void *B1, int64_t m, int64_t ldb, int64_t qb,
-                             float *S, hipStream_t st);
+                             const void *B0, const void *B1, int64_t m, int64_t ncols,
+                             int64_t npad, float *S, hipStream_t st);
+int64_t mfma_col_pad(int64_t ncols);
 hipError_t launch_mfma_gemm(const MfmaArgs &a, hipStream_t st);
 hipError_t launch_mfma_recheck(const MfmaArgs &a, hipStream_t st);
-constexpr int kMfmaCols = 64;  // directions per matrix-core workgroup
 hipError_t launch_init_state(int64_t qb, int64_t d, int64_t n, double *pole, double *best_d,
                              int64_t *best_c, hipStream_t st);
 hipError_t launch_finalize(int64_t qb, int64_t d, int64_t n, bool half, const double *pole,

@@ -29,9 +29,6 @@ typedef __attribute__((ext_vector_type(8))) __bf16 bf16x8;
 typedef __attribute__((ext_vector_type(4))) float f32x4;
 typedef __attribute__((ext_vector_type(16))) float f32x16;
 
-constexpr int kNJ = 2;            // 32-direction tiles per wave
-constexpr int kRowsPerWave = 32;  // points per wave tile
-constexpr int kWaves = 4;
 
 // bfloat16 of a binary64 value, round to nearest even through binary32.
 __device__ __forceinline__ __bf16 to_bf16(double v) { return (__bf16)(float)v; }
@@ -96,15 +93,17 @@ __global__ __launch_bounds__(256) void k_prep_data(const double *__restrict__ X,
 }
 
 // Per refinement: the directions (binary64, [q][d][ldm] in UT) in the GEMM's
-// operand format.  FOLD (sign counts): the centring term is folded in and
-// cmarg[q][j] = kappa |c_j| + slack (binary32, rounded up).  Otherwise (stored
-// projections): the centring columns are zero, cq[q][j] = c_j and eq[q][j]
-// bounds |(s_ij - c_j) - t_ij| for every point i, with t_ij the recipe's
-// binary64 projection: kappa max|a| + canon (max|a| + 2 |z - xbar|).
+// operand format, one operand row per flat column J = q m + j (rows ncols ..
+// npad - 1 are zero).  FOLD (sign counts): the centring term is folded in and
+// cmarg[J] = kappa |c_j| + slack (binary32, rounded up).  Otherwise (stored
+// projections): the centring columns are zero, cq[J] = c_j and eq[J] bounds
+// |(s_ij - c_j) - t_ij| for every point i, with t_ij the recipe's binary64
+// projection: kappa max|a| + canon (max|a| + 2 |z - xbar|).
 template <int PREC, bool FOLD>
 __global__ __launch_bounds__(64) void k_prep_dirs(const double *__restrict__ UT, int64_t d,
-                                                  int64_t m, int64_t ldm, int64_t ldb,
-                                                  int64_t kp, const double *__restrict__ Zb,
+                                                  int64_t m, int64_t ldm, int64_t ncols,
+                                                  int64_t npad, int64_t kp,
+                                                  const double *__restrict__ Zb,
                                                   const double *__restrict__ xbar, double kappa,
                                                   double canon, void *__restrict__ B0,
                                                   void *__restrict__ B1,
@@ -113,14 +112,13 @@ __global__ __launch_bounds__(64) void k_prep_dirs(const double *__restrict__ UT,
                                                   double *__restrict__ cq,
                                                   double *__restrict__ eq)
 {
-    const int64_t j = (int64_t)blockIdx.x * 64 + threadIdx.x;
-    const int64_t qi = blockIdx.y;
-    if (j >= ldb) return;
-    const int64_t off = (qi * ldb + j) * kp;
+    const int64_t J = (int64_t)blockIdx.x * 64 + threadIdx.x;
+    if (J >= npad) return;
+    const int64_t off = J * kp;
     __bf16 *bh = (__bf16 *)B0 + off;
     __bf16 *bl = (__bf16 *)B1 + off;
     float *bf = (float *)B0 + off;
-    if (j >= m) {
+    if (J >= ncols) {
         for (int64_t c = 0; c < kp; ++c) {
             if (PREC == MFMA_BF16) {
                 bh[c] = (__bf16)0.0f;
@@ -130,13 +128,14 @@ __global__ __launch_bounds__(64) void k_prep_dirs(const double *__restrict__ UT,
             }
         }
         if (FOLD) {
-            cmarg[qi * ldb + j] = 0.0f;
+            cmarg[J] = 0.0f;
         } else {
-            cq[qi * ldb + j] = 0.0;
-            eq[qi * ldb + j] = 0.0;
+            cq[J] = 0.0;
+            eq[J] = 0.0;
         }
         return;
     }
+    const int64_t qi = J / m, j = J - qi * m;
     const double *u = UT + qi * d * ldm + j;
     const double *z = Zb + qi * d;
     double cj = 0.0, bn = 0.0;
@@ -178,18 +177,23 @@ __global__ __launch_bounds__(64) void k_prep_dirs(const double *__restrict__ UT,
     // kappa' |a_i| is added per element
     if (FOLD) {
         const double mc = kappa * fabs(cj) + canon * sqrt(bn) * 1.000001 + 1e-300;
-        cmarg[qi * ldb + j] = (float)mc * (1.0f + 1e-6f);
+        cmarg[J] = (float)mc * (1.0f + 1e-6f);
     } else {
         const double am = (double)*amax;
-        cq[qi * ldb + j] = cj;
-        eq[qi * ldb + j] = (kappa * am + canon * (am + 2.0 * sqrt(bn) * 1.000001)) * 1.000001;
+        cq[J] = cj;
+        eq[J] = (kappa * am + canon * (am + 2.0 * sqrt(bn) * 1.000001)) * 1.000001;
     }
 }
 
 // ---------------------------------------------------------------------------
-// GEMM + sign epilogue.  Workgroup: 4 waves x 32 points, all sharing
-// kNJ x 32 directions of one query.  Lane layouts (lr = lane % 32,
-// lh = lane / 32):
+// GEMM with a sign-count or a store epilogue.  C = A B^T with A the centred
+// data [n][kp] and B the direction operands [npad][kp] (flat columns
+// J = q m + j of the batch).  Workgroup: 4 waves, a tile of kTM = 256 points
+// x kTN = 128 columns; wave w owns points 64 w .. 64 w + 63 (two 32-row MFMA
+// tiles) against all four 32-column tiles.  B is staged through LDS in K
+// chunks of kKC (shared by the four waves); A fragments come straight from
+// global memory (each row is read by one wave only).  Lane layouts
+// (lr = lane % 32, lh = lane / 32):
 //   v_mfma_f32_32x32x16_bf16: A row lr holds K elements 8 lh .. 8 lh + 7 of
 //     the 16-step, B column lr likewise;
 //   v_mfma_f32_32x32x2_f32: A row lr holds K element lh of the 2-step, B
@@ -199,171 +203,232 @@ __global__ __launch_bounds__(64) void k_prep_dirs(const double *__restrict__ UT,
 //     assignment, so the sum is the full dot product);
 //   both: accumulator r holds row (r / 4) 8 + 4 lh + r % 4 of column lr.
 // ---------------------------------------------------------------------------
-template <int PREC>
-__device__ __forceinline__ void gemm_tile(const void *__restrict__ A0,
-                                          const void *__restrict__ A1, int64_t n, int64_t kp,
-                                          const void *__restrict__ B0,
-                                          const void *__restrict__ B1, int64_t ldb, int64_t qi,
-                                          int64_t j0, int64_t row0, int lr, int lh,
-                                          f32x16 (&acc)[kNJ])
-{
-#pragma unroll
-    for (int t = 0; t < kNJ; ++t)
-#pragma unroll
-        for (int r = 0; r < 16; ++r) acc[t][r] = 0.0f;
+constexpr int kTM = 256, kTN = 128, kKC = 64;
+constexpr int kLdsRow16 = kKC + 8;   // bf16 elements per staged B row (padded)
+constexpr int kLdsRow32 = kKC + 4;   // binary32 elements per staged B row (padded)
 
-    int64_t arow = row0 + lr;
-    if (arow > n - 1) arow = n - 1;  // clamp; results of rows >= n are ignored
-    if (PREC == MFMA_BF16) {
-        const __bf16 *ah = (const __bf16 *)A0 + arow * kp + 8 * lh;
-        const __bf16 *al = (const __bf16 *)A1 + arow * kp + 8 * lh;
-        const __bf16 *bh[kNJ], *bl[kNJ];
+struct GemmLds {
+    union {
+        __bf16 bh[kTN * kLdsRow16 * 2];  // hi rows, then lo rows
+        float bf[kTN * kLdsRow32];
+    };
+    uint32_t red[4][kTN][2];
+    float an[kTM];   // norm bounds of the tile's points (sign epilogue)
+    uint32_t unc[4][4][64];  // per wave, column tile and lane: uncertain elements
+};
+
+enum { EPI_SIGN = 0, EPI_STORE = 1 };
+
+template <int PREC>
+__device__ __forceinline__ void gemm_block(const void *__restrict__ A0,
+                                           const void *__restrict__ A1, int64_t n, int64_t kp,
+                                           const void *__restrict__ B0,
+                                           const void *__restrict__ B1, int64_t J0,
+                                           int64_t row0, GemmLds &L, f32x16 (&acc)[2][4])
+{
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int lr = lane & 31, lh = lane >> 5;
 #pragma unroll
-        for (int t = 0; t < kNJ; ++t) {
-            const int64_t col = qi * ldb + j0 + 32 * t + lr;  // < qb * ldb: ldb covers the grid
-            bh[t] = (const __bf16 *)B0 + col * kp + 8 * lh;
-            bl[t] = (const __bf16 *)B1 + col * kp + 8 * lh;
-        }
-        for (int64_t k = 0; k < kp; k += 16) {
-            const bf16x8 a_h = *(const bf16x8 *)(ah + k);
-            const bf16x8 a_l = *(const bf16x8 *)(al + k);
+    for (int rt = 0; rt < 2; ++rt)
 #pragma unroll
-            for (int t = 0; t < kNJ; ++t) {
-                const bf16x8 b_h = *(const bf16x8 *)(bh[t] + k);
-                const bf16x8 b_l = *(const bf16x8 *)(bl[t] + k);
-                acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a_h, b_h, acc[t], 0, 0, 0);
-                acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a_h, b_l, acc[t], 0, 0, 0);
-                acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a_l, b_h, acc[t], 0, 0, 0);
+        for (int ct = 0; ct < 4; ++ct)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) acc[rt][ct][r] = 0.0f;
+    int64_t ar[2];
+#pragma unroll
+    for (int rt = 0; rt < 2; ++rt) {
+        ar[rt] = row0 + rt * 32 + lr;
+        if (ar[rt] > n - 1) ar[rt] = n - 1;  // clamp; rows >= n are ignored
+    }
+    for (int64_t k0 = 0; k0 < kp; k0 += kKC) {
+        const int kc = (int)((kp - k0) < kKC ? (kp - k0) : kKC);
+        // stage B[J0 .. J0 + 127][k0 .. k0 + kc) in LDS, 16 bytes per copy
+        if (PREC == MFMA_BF16) {
+            const int per_row = kc / 8;  // 16-byte pieces per row and term
+            for (int p = tid; p < kTN * per_row * 2; p += 256) {
+                const int term = p / (kTN * per_row);
+                const int q = p - term * kTN * per_row;
+                const int row = q / per_row, piece = q - row * per_row;
+                const __bf16 *src = (const __bf16 *)(term ? B1 : B0) + (J0 + row) * kp + k0 +
+                                    piece * 8;
+                *(bf16x8 *)(L.bh + (term * kTN + row) * kLdsRow16 + piece * 8) =
+                    *(const bf16x8 *)src;
+            }
+        } else {
+            const int per_row = kc / 4;
+            for (int p = tid; p < kTN * per_row; p += 256) {
+                const int row = p / per_row, piece = p - row * per_row;
+                const float *src = (const float *)B0 + (J0 + row) * kp + k0 + piece * 4;
+                *(f32x4 *)(L.bf + row * kLdsRow32 + piece * 4) = *(const f32x4 *)src;
             }
         }
-    } else {
-        const float *af = (const float *)A0 + arow * kp + 4 * lh;
-        const float *bf[kNJ];
+        __syncthreads();
+        if (PREC == MFMA_BF16) {
+            for (int kk = 0; kk < kc; kk += 16) {
+                bf16x8 ah[2], al[2];
 #pragma unroll
-        for (int t = 0; t < kNJ; ++t) {
-            const int64_t col = qi * ldb + j0 + 32 * t + lr;
-            bf[t] = (const float *)B0 + col * kp + 4 * lh;
-        }
-        for (int64_t k = 0; k < kp; k += 8) {
-            const f32x4 a = *(const f32x4 *)(af + k);
+                for (int rt = 0; rt < 2; ++rt) {
+                    ah[rt] = *(const bf16x8 *)((const __bf16 *)A0 + ar[rt] * kp + k0 + kk + 8 * lh);
+                    al[rt] = *(const bf16x8 *)((const __bf16 *)A1 + ar[rt] * kp + k0 + kk + 8 * lh);
+                }
 #pragma unroll
-            for (int t = 0; t < kNJ; ++t) {
-                const f32x4 b = *(const f32x4 *)(bf[t] + k);
-                acc[t] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[0], b[0], acc[t], 0, 0, 0);
-                acc[t] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[1], b[1], acc[t], 0, 0, 0);
-                acc[t] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[2], b[2], acc[t], 0, 0, 0);
-                acc[t] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[3], b[3], acc[t], 0, 0, 0);
+                for (int ct = 0; ct < 4; ++ct) {
+                    const int col = ct * 32 + lr;
+                    const bf16x8 bh = *(const bf16x8 *)(L.bh + col * kLdsRow16 + kk + 8 * lh);
+                    const bf16x8 bl =
+                        *(const bf16x8 *)(L.bh + (kTN + col) * kLdsRow16 + kk + 8 * lh);
+#pragma unroll
+                    for (int rt = 0; rt < 2; ++rt) {
+                        acc[rt][ct] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[rt], bh,
+                                                                              acc[rt][ct], 0, 0, 0);
+                        acc[rt][ct] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[rt], bl,
+                                                                              acc[rt][ct], 0, 0, 0);
+                        acc[rt][ct] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[rt], bh,
+                                                                              acc[rt][ct], 0, 0, 0);
+                    }
+                }
+            }
+        } else {
+            for (int kk = 0; kk < kc; kk += 8) {
+                f32x4 a[2];
+#pragma unroll
+                for (int rt = 0; rt < 2; ++rt)
+                    a[rt] = *(const f32x4 *)((const float *)A0 + ar[rt] * kp + k0 + kk + 4 * lh);
+#pragma unroll
+                for (int ct = 0; ct < 4; ++ct) {
+                    const int col = ct * 32 + lr;
+                    const f32x4 b = *(const f32x4 *)(L.bf + col * kLdsRow32 + kk + 4 * lh);
+#pragma unroll
+                    for (int rt = 0; rt < 2; ++rt) {
+                        acc[rt][ct] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[rt][0], b[0],
+                                                                           acc[rt][ct], 0, 0, 0);
+                        acc[rt][ct] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[rt][1], b[1],
+                                                                           acc[rt][ct], 0, 0, 0);
+                        acc[rt][ct] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[rt][2], b[2],
+                                                                           acc[rt][ct], 0, 0, 0);
+                        acc[rt][ct] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[rt][3], b[3],
+                                                                           acc[rt][ct], 0, 0, 0);
+                    }
+                }
             }
         }
+        __syncthreads();  // the next chunk overwrites the staged B
     }
 }
 
-template <int PREC>
-__global__ __launch_bounds__(256) void k_gemm_sign(
+template <int PREC, int EPI>
+__global__ __launch_bounds__(256) void k_gemm(
     const void *__restrict__ A0, const void *__restrict__ A1,
     const float *__restrict__ anorm, int64_t n, int64_t kp,
     const void *__restrict__ B0, const void *__restrict__ B1,
-    const float *__restrict__ cmarg, int64_t m, int64_t ldm, int64_t ldb, float kappa_a,
+    const float *__restrict__ cmarg, int64_t m, int64_t ncols, int64_t ldm, float kappa_a,
     uint32_t *__restrict__ cnt, uint64_t *__restrict__ queue, uint32_t *__restrict__ qcount,
-    uint64_t qcap)
+    uint64_t qcap, float *__restrict__ S)
 {
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int64_t qi = blockIdx.y;
-    const int64_t j0 = (int64_t)blockIdx.x * (32 * kNJ);
-    const int64_t row0 = (int64_t)blockIdx.z * (kRowsPerWave * kWaves) + wave * kRowsPerWave;
+    __shared__ GemmLds L;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int lr = lane & 31, lh = lane >> 5;
-    f32x16 acc[kNJ];
-    gemm_tile<PREC>(A0, A1, n, kp, B0, B1, ldb, qi, j0, row0, lr, lh, acc);
-
-    // epilogue: per lane, one column per tile, 16 rows
-    constexpr bool kPlain = PREC == MFMA_F32_PLAIN;
-    float an[16];
-#pragma unroll
-    for (int r = 0; r < 16; ++r) {
-        const int64_t i = row0 + (r >> 2) * 8 + lh * 4 + (r & 3);
-        an[r] = (!kPlain && i < n) ? anorm[i] : 0.0f;
+    const int64_t J0 = (int64_t)blockIdx.x * kTN;
+    const int64_t row0 = (int64_t)blockIdx.y * kTM + wave * 64;
+    if (EPI == EPI_SIGN && PREC != MFMA_F32_PLAIN) {
+        const int64_t i = (int64_t)blockIdx.y * kTM + tid;  // 256 threads = kTM rows
+        L.an[tid] = i < n ? anorm[i] : 0.0f;
     }
-    __shared__ uint32_t red[kWaves][32 * kNJ][2];
+    f32x16 acc[2][4];
+    gemm_block<PREC>(A0, A1, n, kp, B0, B1, J0, row0, L, acc);  // its barriers publish L.an
+
+    if (EPI == EPI_STORE) {
+        // S[J][i]: lane lr writes rows (r / 4) 8 + 4 lh .. + 3 of column J
 #pragma unroll
-    for (int t = 0; t < kNJ; ++t) {
-        const int64_t j = j0 + 32 * t + lr;
-        const float cm = (!kPlain && j < m) ? cmarg[qi * ldb + j] : 0.0f;
-        uint32_t pos = 0, neg = 0;
+        for (int ct = 0; ct < 4; ++ct) {
+            const int64_t J = J0 + ct * 32 + lr;
+            if (J >= ncols) continue;
+            float *col = S + J * n;
 #pragma unroll
-        for (int r = 0; r < 16; ++r) {
-            const int64_t i = row0 + (r >> 2) * 8 + lh * 4 + (r & 3);
-            const bool live = i < n && j < m;
-            const float v = acc[t][r];
-            if (kPlain) {
-                // sign of t^ itself; zero counts on both sides
-                pos += (live && v >= 0.0f) ? 1u : 0u;
-                neg += (live && v <= 0.0f) ? 1u : 0u;
-                continue;
+            for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+                for (int g = 0; g < 4; ++g) {
+                    const int64_t i = row0 + rt * 32 + g * 8 + lh * 4;
+                    if (i + 3 < n && (n & 3) == 0) {
+                        f32x4 v = {acc[rt][ct][4 * g], acc[rt][ct][4 * g + 1],
+                                   acc[rt][ct][4 * g + 2], acc[rt][ct][4 * g + 3]};
+                        *(f32x4 *)(col + i) = v;
+                    } else {
+#pragma unroll
+                        for (int e = 0; e < 4; ++e)
+                            if (i + e < n) col[i + e] = acc[rt][ct][4 * g + e];
+                    }
+                }
+        }
+        return;
+    }
+
+    constexpr bool kPlain = PREC == MFMA_F32_PLAIN;
+    const int rows_left = (int)(n - (int64_t)blockIdx.y * kTM);  // > 0
+#pragma unroll
+    for (int ct = 0; ct < 4; ++ct) {
+        const int64_t J = J0 + ct * 32 + lr;
+        const bool jlive = J < ncols;
+        const float cm = (!kPlain && jlive) ? cmarg[J] : 0.0f;
+        uint32_t pos = 0, neg = 0, unc = 0;
+#pragma unroll
+        for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const int il = wave * 64 + rt * 32 + (r >> 2) * 8 + lh * 4 + (r & 3);
+                const bool live = jlive && il < rows_left;
+                const float v = acc[rt][ct][r];
+                if (kPlain) {
+                    // sign of t^ itself; zero counts on both sides
+                    pos += (live && v >= 0.0f) ? 1u : 0u;
+                    neg += (live && v <= 0.0f) ? 1u : 0u;
+                    continue;
+                }
+                const float marg = fmaf(kappa_a, L.an[il], cm);
+                const bool sp = v > marg, sn = v < -marg;
+                pos += (live && sp) ? 1u : 0u;
+                neg += (live && sn) ? 1u : 0u;
+                unc |= (live && !sp && !sn) ? (1u << (rt * 16 + r)) : 0u;
             }
-            const float marg = fmaf(kappa_a, an[r], cm);
-            const bool sp = live && v > marg;
-            const bool sn = live && v < -marg;
-            pos += sp ? 1u : 0u;
-            neg += sn ? 1u : 0u;
-            if (live && !sp && !sn) {
+        if (!kPlain) L.unc[wave][ct][lane] = unc;
+        __builtin_amdgcn_sched_barrier(0);
+        // lanes l and l + 32 hold the same column
+        pos += (uint32_t)__shfl_xor((int)pos, 32);
+        neg += (uint32_t)__shfl_xor((int)neg, 32);
+        if (lh == 0) {
+            L.red[wave][ct * 32 + lr][0] = neg;  // t < 0: counts for "<= 0"
+            L.red[wave][ct * 32 + lr][1] = pos;  // t > 0: counts for ">= 0"
+        }
+    }
+    if (!kPlain) {
+        // uncertain signs (rare): queue (query, direction, point)
+        for (int ct = 0; ct < 4; ++ct) {
+            uint32_t unc = L.unc[wave][ct][lane];
+            if (!unc) continue;
+            const int64_t J = J0 + ct * 32 + lr;
+            const int64_t qi = J / m, j = J - qi * m;
+            while (unc) {
+                const int b = __builtin_ctz(unc);
+                unc &= unc - 1;
+                const int rt = b >> 4, r = b & 15;
+                const int64_t i = (int64_t)blockIdx.y * kTM + wave * 64 + rt * 32 + (r >> 2) * 8 +
+                                  lh * 4 + (r & 3);
                 const uint32_t slot = atomicAdd(qcount, 1u);
                 if ((uint64_t)slot < qcap)
                     queue[slot] = ((uint64_t)qi << 48) | ((uint64_t)j << 32) | (uint64_t)i;
             }
         }
-        // lanes l and l + 32 hold the same column
-        pos += (uint32_t)__shfl_xor((int)pos, 32);
-        neg += (uint32_t)__shfl_xor((int)neg, 32);
-        if (lh == 0) {
-            red[wave][32 * t + lr][0] = neg;  // t < 0: counts for "<= 0"
-            red[wave][32 * t + lr][1] = pos;  // t > 0: counts for ">= 0"
-        }
     }
     __syncthreads();
-    if (threadIdx.x < 32 * kNJ * 2) {
-        const int jj = threadIdx.x >> 1, w = threadIdx.x & 1;
-        const int64_t j = j0 + jj;
+    {
+        const int jj = tid >> 1, w = tid & 1;  // 256 threads = 128 columns x 2 sides
+        const int64_t J = J0 + jj;
         uint32_t s = 0;
 #pragma unroll
-        for (int wv = 0; wv < kWaves; ++wv) s += red[wv][jj][w];
-        if (j < m && s) atomicAdd(&cnt[(qi * ldm + j) * 2 + w], s);
-    }
-}
-
-// GEMM with a store epilogue: the centred projections s_ij = a_i.u_j
-// (binary32) of the batch, column (query, direction) after column, for the
-// selects of projection and asymmetric projection depth.  Lane lr writes
-// rows (r / 4) 8 + 4 lh .. + 3 of its column as one 16-byte store.
-template <int PREC>
-__global__ __launch_bounds__(256) void k_gemm_store(const void *__restrict__ A0,
-                                                    const void *__restrict__ A1, int64_t n,
-                                                    int64_t kp, const void *__restrict__ B0,
-                                                    const void *__restrict__ B1, int64_t m,
-                                                    int64_t ldb, float *__restrict__ S)
-{
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int64_t qi = blockIdx.y;
-    const int64_t j0 = (int64_t)blockIdx.x * (32 * kNJ);
-    const int64_t row0 = (int64_t)blockIdx.z * (kRowsPerWave * kWaves) + wave * kRowsPerWave;
-    const int lr = lane & 31, lh = lane >> 5;
-    f32x16 acc[kNJ];
-    gemm_tile<PREC>(A0, A1, n, kp, B0, B1, ldb, qi, j0, row0, lr, lh, acc);
-#pragma unroll
-    for (int t = 0; t < kNJ; ++t) {
-        const int64_t j = j0 + 32 * t + lr;
-        if (j >= m) continue;
-        float *col = S + (qi * m + j) * n;
-#pragma unroll
-        for (int g = 0; g < 4; ++g) {
-            const int64_t i = row0 + g * 8 + lh * 4;
-            if (i + 3 < n && (n & 3) == 0) {
-                f32x4 v = {acc[t][4 * g], acc[t][4 * g + 1], acc[t][4 * g + 2], acc[t][4 * g + 3]};
-                *(f32x4 *)(col + i) = v;
-            } else {
-#pragma unroll
-                for (int e = 0; e < 4; ++e)
-                    if (i + e < n) col[i + e] = acc[t][4 * g + e];
-            }
+        for (int wv = 0; wv < 4; ++wv) s += L.red[wv][jj][w];
+        if (J < ncols && s) {
+            const int64_t qi = J / m, j = J - qi * m;
+            atomicAdd(&cnt[(qi * ldm + j) * 2 + w], s);
         }
     }
 }
@@ -468,17 +533,17 @@ hipError_t launch_mfma_prep(int prec, const double *X, int64_t n, int64_t d, dou
 }
 
 hipError_t launch_mfma_dirs(int prec, bool fold, const double *UT, int64_t d, int64_t m,
-                            int64_t ldm, int64_t ldb, int64_t qb, const double *Zb,
+                            int64_t ldm, int64_t ncols, int64_t npad, const double *Zb,
                             const double *xbar, void *B0, void *B1, float *cmarg,
                             const float *amax, double *cq, double *eq, hipStream_t st)
 {
     double kappa, canon;
     const int64_t kp = mfma_kpad(prec, d);
     mfma_margins(prec, d, kp, &kappa, &canon);
-    dim3 grid((unsigned)((ldb + 63) / 64), (unsigned)qb);
+    dim3 grid((unsigned)((npad + 63) / 64));
 #define RRS_DIRS(P, F)                                                                        \
-    hipLaunchKernelGGL((k_prep_dirs<P, F>), grid, dim3(64), 0, st, UT, d, m, ldm, ldb, kp, Zb, \
-                       xbar, kappa, canon, B0, B1, cmarg, amax, cq, eq)
+    hipLaunchKernelGGL((k_prep_dirs<P, F>), grid, dim3(64), 0, st, UT, d, m, ldm, ncols, npad, \
+                       kp, Zb, xbar, kappa, canon, B0, B1, cmarg, amax, cq, eq)
     if (prec == MFMA_BF16) {
         if (fold)
             RRS_DIRS(MFMA_BF16, true);
@@ -494,20 +559,24 @@ hipError_t launch_mfma_dirs(int prec, bool fold, const double *UT, int64_t d, in
     return hipGetLastError();
 }
 
+int64_t mfma_col_pad(int64_t ncols) { return (ncols + kTN - 1) / kTN * kTN; }
+
 hipError_t launch_mfma_store(int prec, const void *A0, const void *A1, int64_t n, int64_t d,
-                             const void *B0, const void *B1, int64_t m, int64_t ldb, int64_t qb,
-                             float *S, hipStream_t st)
+                             const void *B0, const void *B1, int64_t m, int64_t ncols,
+                             int64_t npad, float *S, hipStream_t st)
 {
     const int64_t kp = mfma_kpad(prec, d);
-    dim3 grid((unsigned)((m + 32 * kNJ - 1) / (32 * kNJ)), (unsigned)qb,
-              (unsigned)((n + kRowsPerWave * kWaves - 1) / (kRowsPerWave * kWaves)));
-    if (ldb < (int64_t)grid.x * 32 * kNJ) return hipErrorInvalidValue;
+    dim3 grid((unsigned)((ncols + kTN - 1) / kTN), (unsigned)((n + kTM - 1) / kTM));
+    if (npad < (int64_t)grid.x * kTN) return hipErrorInvalidValue;
+#define RRS_STORE(P)                                                                          \
+    hipLaunchKernelGGL((k_gemm<P, EPI_STORE>), grid, dim3(256), 0, st, A0, A1, nullptr, n, kp, \
+                       B0, B1, nullptr, m, ncols, (int64_t)0, 0.0f, nullptr, nullptr, nullptr, \
+                       (uint64_t)0, S)
     if (prec == MFMA_BF16)
-        hipLaunchKernelGGL(k_gemm_store<MFMA_BF16>, grid, dim3(256), 0, st, A0, A1, n, kp, B0, B1,
-                           m, ldb, S);
+        RRS_STORE(MFMA_BF16);
     else
-        hipLaunchKernelGGL(k_gemm_store<MFMA_F32>, grid, dim3(256), 0, st, A0, A1, n, kp, B0, B1,
-                           m, ldb, S);
+        RRS_STORE(MFMA_F32);
+#undef RRS_STORE
     return hipGetLastError();
 }
 
@@ -517,13 +586,13 @@ hipError_t launch_mfma_gemm(const MfmaArgs &a, hipStream_t st)
     const int64_t kp = mfma_kpad(a.prec, a.d);
     mfma_margins(a.prec, a.d, kp, &kappa, &canon);
     const float kappa_a = (float)((kappa + canon) * 1.000001);
-    dim3 grid((unsigned)((a.m + 32 * kNJ - 1) / (32 * kNJ)), (unsigned)a.qb,
-              (unsigned)((a.n + kRowsPerWave * kWaves - 1) / (kRowsPerWave * kWaves)));
-    if (a.ldb < (int64_t)grid.x * 32 * kNJ) return hipErrorInvalidValue;
+    const int64_t ncols = a.qb * a.m;
+    dim3 grid((unsigned)((ncols + kTN - 1) / kTN), (unsigned)((a.n + kTM - 1) / kTM));
+    if (a.npad < (int64_t)grid.x * kTN) return hipErrorInvalidValue;
 #define RRS_GEMM(P)                                                                           \
-    hipLaunchKernelGGL(k_gemm_sign<P>, grid, dim3(256), 0, st, a.A0, a.A1, a.anorm, a.n, kp,  \
-                       a.B0, a.B1, a.cmarg, a.m, a.ldm, a.ldb, kappa_a, a.cnt, a.queue,       \
-                       a.qcount, a.qcap)
+    hipLaunchKernelGGL((k_gemm<P, EPI_SIGN>), grid, dim3(256), 0, st, a.A0, a.A1, a.anorm, a.n, \
+                       kp, a.B0, a.B1, a.cmarg, a.m, ncols, a.ldm, kappa_a, a.cnt, a.queue,    \
+                       a.qcount, a.qcap, nullptr)
     if (a.prec == MFMA_BF16)
         RRS_GEMM(MFMA_BF16);
     else if (a.prec == MFMA_F32)

@@ -129,6 +129,66 @@ __device__ __forceinline__ double key_hi_value(uint32_t K, uint32_t tau)
     return K == 0u ? hi_to_double(tau) : hi_to_double(K + tau);
 }
 
+// Where a select reads the column's binary32 projections from.
+// StreamSrc: global memory, 4 loads in flight per lane (any n).
+struct StreamSrc {
+    const float *s;
+    int64_t n;
+    __device__ __forceinline__ float sample(int slot) const
+    {
+        return s[((2 * (int64_t)slot + 1) * n) / 128];
+    }
+    template <class F>
+    __device__ __forceinline__ void each(F &&f) const
+    {
+        for (int64_t i0 = threadIdx.x; i0 < n; i0 += (int64_t)kUnroll * kT) {
+            float t[kUnroll];
+#pragma unroll
+            for (int u = 0; u < kUnroll; ++u) {
+                const int64_t i = i0 + (int64_t)u * kT;
+                t[u] = i < n ? s[i] : 0.0f;
+            }
+#pragma unroll
+            for (int u = 0; u < kUnroll; ++u) {
+                const int64_t i = i0 + (int64_t)u * kT;
+                f(i, t[u], i < n);
+            }
+        }
+    }
+};
+
+// RegSrc: the column held in registers, VPT values per lane (entry
+// threadIdx.x + kT v in slot v; slots past n are never live).  Every loop
+// over the slots is unrolled with compile-time indices, which keeps the
+// array in registers.
+template <int VPT>
+struct RegSrc {
+    float (&v)[VPT];
+    int64_t n;
+    __device__ __forceinline__ float sample(int slot) const
+    {
+        // slot 16 w + l (wave w, lane l < 16) takes register (2 w + 1) VPT / 8
+        const int w = slot >> 4;
+        float x0 = v[(1 * VPT) / 8], x1 = v[(3 * VPT) / 8];
+        float x2 = v[(5 * VPT) / 8], x3 = v[(7 * VPT) / 8];
+        asm volatile("" : "+v"(x0), "+v"(x1), "+v"(x2), "+v"(x3));
+        return w == 0 ? x0 : w == 1 ? x1 : w == 2 ? x2 : x3;
+    }
+    template <class F>
+    __device__ __forceinline__ void each(F &&f) const
+    {
+        // opaque registers: values derived in an earlier pass (binary64
+        // conversions, keys) are recomputed instead of being kept live
+#pragma unroll
+        for (int u = 0; u < VPT; ++u) asm volatile("" : "+v"(v[u]));
+#pragma unroll
+        for (int u = 0; u < VPT; ++u) {
+            const int64_t i = (int64_t)threadIdx.x + (int64_t)kT * u;
+            f(i, v[u], i < n);
+        }
+    }
+};
+
 // Exact radix select (rank k) over the recomputed values of phase PH.
 template <int PH, bool EXACT>
 __device__ uint64_t rc_radix_kth(const Col &C, double med, uint64_t k, RcShared &sh)
@@ -223,9 +283,10 @@ __device__ uint64_t rc_radix_next(const Col &C, double med, uint64_t k, uint64_t
 // The exact values of ranks k (and k + 1 if pair) in phase PH.  Returns true
 // when the window path served them; then sh.cval[0 .. ncand) holds the
 // window's exact values and *below the number of points under the window.
-template <int PH, bool EXACT>
-__device__ bool rc_select(const Col &C, double med, double sig, double E, uint64_t k, bool pair,
-                          double &a, double &b, uint64_t *below, RcShared &sh, uint32_t *stats)
+template <int PH, bool EXACT, class SRC>
+__device__ bool rc_select(const Col &C, const SRC &src, double med, double sig, double E,
+                          uint64_t k, bool pair, double &a, double &b, uint64_t *below,
+                          RcShared &sh, uint32_t *stats)
 {
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int64_t n = C.n;
@@ -235,12 +296,13 @@ __device__ bool rc_select(const Col &C, double med, double sig, double E, uint64
         sh.below = 0;
         sh.ncand = 0;
     }
-    if (tid < 64) {
-        const int64_t i = ((2 * (int64_t)tid + 1) * n) / 128;
-        const double x = approx_v<PH>((double)C.s[i], sig);
+    // 64 sampled approximations: slot 16 w + l from lane l < 16 of wave w
+    if (lane < 16) {
+        const int slot = wave * 16 + lane;
+        const double x = approx_v<PH>((double)src.sample(slot), sig);
         const uint32_t kx = key32<PH>(x);
-        sh.skey[tid] = key_takes_part<PH>(kx) ? kx : 0xFFFFFFFFu;
-        sh.sval[tid] = x;
+        sh.skey[slot] = key_takes_part<PH>(kx) ? kx : 0xFFFFFFFFu;
+        sh.sval[slot] = x;
     }
     __syncthreads();
     {
@@ -294,22 +356,12 @@ __device__ bool rc_select(const Col &C, double med, double sig, double E, uint64
         const uint32_t Lk = sh.Lk, R = sh.R, bsh = sh.sh, tau = sh.tau;
         uint32_t nbelow = 0;
         const uint32_t dummy = (uint32_t)kBins + (uint32_t)lane;
-        for (int64_t i0 = tid; i0 < n; i0 += (int64_t)kUnroll * kT) {
-            float t[kUnroll];
-#pragma unroll
-            for (int u = 0; u < kUnroll; ++u) {
-                const int64_t i = i0 + (int64_t)u * kT;
-                t[u] = i < n ? C.s[i] : 0.0f;
-            }
-#pragma unroll
-            for (int u = 0; u < kUnroll; ++u) {
-                const bool live = i0 + (int64_t)u * kT < n;
-                const uint32_t kx = bin_key<PH>(approx_v<PH>((double)t[u], sig), tau);
-                const uint32_t dk = kx - Lk;
-                nbelow += (live && kx < Lk) ? 1u : 0u;
-                atomicAdd(&sh.hist[(live && dk <= R) ? (dk >> bsh) : dummy], 1u);
-            }
-        }
+        src.each([&](int64_t, float sv, bool live) {
+            const uint32_t kx = bin_key<PH>(approx_v<PH>((double)sv, sig), tau);
+            const uint32_t dk = kx - Lk;
+            nbelow += (live && kx < Lk) ? 1u : 0u;
+            atomicAdd(&sh.hist[(live && dk <= R) ? (dk >> bsh) : dummy], 1u);
+        });
         for (int off = 32; off > 0; off >>= 1) nbelow += (uint32_t)__shfl_xor((int)nbelow, off);
         if (lane == 0 && nbelow) atomicAdd(&sh.below, nbelow);
         __syncthreads();
@@ -341,25 +393,14 @@ __device__ bool rc_select(const Col &C, double med, double sig, double E, uint64
             if (tid == 0) sh.below = 0;
             __syncthreads();
             nbelow = 0;
-            for (int64_t i0 = tid; i0 < n; i0 += (int64_t)kUnroll * kT) {
-                float t[kUnroll];
-#pragma unroll
-                for (int u = 0; u < kUnroll; ++u) {
-                    const int64_t i = i0 + (int64_t)u * kT;
-                    t[u] = i < n ? C.s[i] : 0.0f;
+            src.each([&](int64_t i, float sv, bool live) {
+                const double x = approx_v<PH>((double)sv, sig);
+                nbelow += (live && x < wlo) ? 1u : 0u;
+                if (live && x >= wlo && x <= whi) {
+                    const uint32_t p = atomicAdd(&sh.ncand, 1u);
+                    if (p < (uint32_t)kCapW) sh.cidx[p] = (uint32_t)i;
                 }
-#pragma unroll
-                for (int u = 0; u < kUnroll; ++u) {
-                    const int64_t i = i0 + (int64_t)u * kT;
-                    if (i >= n) continue;
-                    const double x = approx_v<PH>((double)t[u], sig);
-                    nbelow += (x < wlo) ? 1u : 0u;
-                    if (x >= wlo && x <= whi) {
-                        const uint32_t p = atomicAdd(&sh.ncand, 1u);
-                        if (p < (uint32_t)kCapW) sh.cidx[p] = (uint32_t)i;
-                    }
-                }
-            }
+            });
             for (int off = 32; off > 0; off >>= 1)
                 nbelow += (uint32_t)__shfl_xor((int)nbelow, off);
             if (lane == 0 && nbelow) atomicAdd(&sh.below, nbelow);
@@ -425,9 +466,46 @@ __device__ uint64_t rc_count_le(const Col &C, double med, bool window, uint64_t 
     return r;
 }
 
-template <int NOTION, bool EXACT>
+template <int NOTION, bool EXACT, class SRC>
+__device__ __forceinline__ double rc_depth(const Col &C, const SRC &src, RcShared &sh,
+                                           uint32_t *stats)
+{
+    // rank k of the s values is rank k of the s - c values: the windows live
+    // in s space (|(s - c) - t| <= E moves every statistic by at most E, and
+    // c is common to the column), the candidates' exact values in t space
+    const int64_t n = C.n;
+    const bool odd = (n & 1) != 0;
+    const uint64_t k = odd ? (uint64_t)n / 2 : (uint64_t)n / 2 - 1;
+    double a, b;
+    uint64_t below = 0;
+    const bool win =
+        rc_select<0, EXACT>(C, src, 0.0, 0.0, C.E, k, !odd, a, b, &below, sh, stats);
+    const double med = odd ? a : (a + b) * 0.5;
+    if (NOTION == NOTION_PROJECTION) {
+        double m1, m2;
+        uint64_t b1 = 0;
+        rc_select<1, EXACT>(C, src, med, med + C.c, C.E, k, !odd, m1, m2, &b1, sh, stats);
+        const double mad = odd ? m1 : (m1 + m2) * 0.5;
+        if (mad == 0.0) return (med == 0.0) ? 1.0 : 0.0;
+        return 1.0 / (1.0 + fabs(med) / mad);
+    }
+    const uint64_t nle = rc_count_le<EXACT>(C, med, win, below, sh);
+    const uint64_t npos = (uint64_t)n - nle;
+    const double num = (med < 0.0) ? -med : 0.0;
+    if (npos == 0) return (num == 0.0) ? 1.0 : 0.0;
+    const bool podd = (npos & 1) != 0;
+    const uint64_t kp = nle + (podd ? npos / 2 : npos / 2 - 1);
+    double p1, p2;
+    uint64_t b2 = 0;
+    rc_select<0, EXACT>(C, src, 0.0, 0.0, C.E, kp, !podd, p1, p2, &b2, sh, stats);
+    const double madp = podd ? (p1 - med) : ((p1 - med) + (p2 - med)) * 0.5;
+    return 1.0 / (1.0 + num / madp);
+}
+
+// VPT > 0: the column in registers (n <= kT VPT); VPT == 0: streamed.
+template <int NOTION, bool EXACT, int VPT>
 __global__ __launch_bounds__(kT) void k_select_rc(const float *__restrict__ S, int64_t n,
-                                                  int64_t m, int64_t ldm, int64_t ldb,
+                                                  int64_t m, int64_t ldm,
                                                   const double *__restrict__ cq,
                                                   const double *__restrict__ eq,
                                                   const double *__restrict__ X, int64_t d,
@@ -442,72 +520,61 @@ __global__ __launch_bounds__(kT) void k_select_rc(const float *__restrict__ S, i
     Col C;
     C.s = S + (qi * m + j) * n;
     C.n = n;
-    C.c = cq[qi * ldb + j];
-    C.E = EXACT ? eq[qi * ldb + j] : 0.0;
+    C.c = cq[qi * m + j];
+    C.E = EXACT ? eq[qi * m + j] : 0.0;
     C.X = X;
     C.d = d;
     C.z = Zb + qi * d;
     C.u = UT + qi * d * ldm + j;
     C.ldm = ldm;
-    // rank k of the s values is rank k of the s - c values: the windows live
-    // in s space (|(s - c) - t| <= E moves every statistic by at most E, and
-    // c is common to the column), the candidates' exact values in t space
-    const bool odd = (n & 1) != 0;
-    const uint64_t k = odd ? (uint64_t)n / 2 : (uint64_t)n / 2 - 1;
-    double a, b;
-    uint64_t below = 0;
-    const bool win = rc_select<0, EXACT>(C, 0.0, 0.0, C.E, k, !odd, a, b, &below, sh, stats);
-    const double med = odd ? a : (a + b) * 0.5;
     double D;
-    if (NOTION == NOTION_PROJECTION) {
-        double m1, m2;
-        uint64_t b1 = 0;
-        rc_select<1, EXACT>(C, med, med + C.c, C.E, k, !odd, m1, m2, &b1, sh, stats);
-        const double mad = odd ? m1 : (m1 + m2) * 0.5;
-        if (mad == 0.0)
-            D = (med == 0.0) ? 1.0 : 0.0;
-        else
-            D = 1.0 / (1.0 + fabs(med) / mad);
+    if (VPT == 0) {
+        D = rc_depth<NOTION, EXACT>(C, StreamSrc{C.s, n}, sh, stats);
     } else {
-        const uint64_t nle = rc_count_le<EXACT>(C, med, win, below, sh);
-        const uint64_t npos = (uint64_t)n - nle;
-        const double num = (med < 0.0) ? -med : 0.0;
-        if (npos == 0) {
-            D = (num == 0.0) ? 1.0 : 0.0;
-        } else {
-            const bool podd = (npos & 1) != 0;
-            const uint64_t kp = nle + (podd ? npos / 2 : npos / 2 - 1);
-            double p1, p2;
-            uint64_t b2 = 0;
-            rc_select<0, EXACT>(C, 0.0, 0.0, C.E, kp, !podd, p1, p2, &b2, sh, stats);
-            const double madp = podd ? (p1 - med) : ((p1 - med) + (p2 - med)) * 0.5;
-            D = 1.0 / (1.0 + num / madp);
+        constexpr int V = VPT > 0 ? VPT : 1;
+        float v[V];
+#pragma unroll
+        for (int u = 0; u < V; ++u) {
+            const int64_t i = (int64_t)threadIdx.x + (int64_t)kT * u;
+            v[u] = i < n ? C.s[i] : 0.0f;
         }
+        D = rc_depth<NOTION, EXACT>(C, RegSrc<V>{v, n}, sh, stats);
     }
     if (threadIdx.x == 0) Dj[qi * ldm + j] = D;
+}
+
+template <int NOTION, bool EXACT, int VPT>
+hipError_t launch_rc(const SelectRcArgs &a, hipStream_t st)
+{
+    dim3 grid((unsigned)a.m, (unsigned)a.qb);
+    hipLaunchKernelGGL((k_select_rc<NOTION, EXACT, VPT>), grid, dim3(kT), 0, st, a.S, a.n, a.m,
+                       a.ldm, a.cq, a.eq, a.X, a.d, a.Z, a.UT, a.Dj, a.stats);
+    return hipGetLastError();
+}
+
+template <int NOTION, bool EXACT>
+hipError_t launch_rc_vpt(const SelectRcArgs &a, hipStream_t st)
+{
+    const int64_t vpt = (a.n + kT - 1) / kT;
+    if (vpt <= 4) return launch_rc<NOTION, EXACT, 4>(a, st);
+    if (vpt <= 8) return launch_rc<NOTION, EXACT, 8>(a, st);
+    if (vpt <= 16) return launch_rc<NOTION, EXACT, 16>(a, st);
+    if (vpt <= 24) return launch_rc<NOTION, EXACT, 24>(a, st);
+    if (vpt <= 32) return launch_rc<NOTION, EXACT, 32>(a, st);
+    if (vpt <= 40) return launch_rc<NOTION, EXACT, 40>(a, st);
+    if (vpt <= 48) return launch_rc<NOTION, EXACT, 48>(a, st);
+    if (vpt <= 64) return launch_rc<NOTION, EXACT, 64>(a, st);
+    return launch_rc<NOTION, EXACT, 0>(a, st);
 }
 
 }  // namespace
 
 hipError_t launch_select_rc(const SelectRcArgs &a, int notion, bool exact, hipStream_t st)
 {
-    dim3 grid((unsigned)a.m, (unsigned)a.qb);
-#define RRS_SEL(N, E)                                                                         \
-    hipLaunchKernelGGL((k_select_rc<N, E>), grid, dim3(kT), 0, st, a.S, a.n, a.m, a.ldm, a.ldb, \
-                       a.cq, a.eq, a.X, a.d, a.Z, a.UT, a.Dj, a.stats)
-    if (notion == NOTION_PROJECTION) {
-        if (exact)
-            RRS_SEL(NOTION_PROJECTION, true);
-        else
-            RRS_SEL(NOTION_PROJECTION, false);
-    } else {
-        if (exact)
-            RRS_SEL(NOTION_APD, true);
-        else
-            RRS_SEL(NOTION_APD, false);
-    }
-#undef RRS_SEL
-    return hipGetLastError();
+    if (notion == NOTION_PROJECTION)
+        return exact ? launch_rc_vpt<NOTION_PROJECTION, true>(a, st)
+                     : launch_rc_vpt<NOTION_PROJECTION, false>(a, st);
+    return exact ? launch_rc_vpt<NOTION_APD, true>(a, st) : launch_rc_vpt<NOTION_APD, false>(a, st);
 }
 
 }  // namespace rrs
