@@ -103,7 +103,17 @@ typedef struct {
                                  halfspace, binary64 bits otherwise) */
     size_t workspace_limit;   /* bytes the per-refinement scratch may use;
                                  0: library default */
+    uint32_t flags;           /* RRS_FLAG_* (default 0) */
+    uint32_t reserved;        /* must be 0 */
 } rrs_opts;
+
+/* flags: RRS_FLAG_GRAPH -- the call's device work (data preparation and the
+ * whole refinement chain) is captured once into a HIP graph and replayed by
+ * later calls with the same arguments (sizes, hyper-parameters, seed,
+ * precision, pointers and stream); needs device_ptrs == 1 and no profiling.
+ * Replays run exactly the captured kernels, so results are identical to the
+ * eager calls.  rrs_release_workspace() drops the cached graphs. */
+#define RRS_FLAG_GRAPH 1u
 
 /* Halfspace (Tukey) depth, Sec. 2: min(#{x_i.u <= z.u}, #{x_i.u >= z.u}) / n,
  * minimised over the RRS directions.  count (may be NULL) receives the

@@ -7,6 +7,7 @@
 
 #include <cmath>
 #include <cstring>
+#include <algorithm>
 #include <map>
 #include <mutex>
 
@@ -26,10 +27,28 @@ struct Arena {
 };
 std::map<int, Arena> g_arenas;
 
+// Captured calls (RRS_FLAG_GRAPH), keyed by every argument that shapes the
+// captured work, including the pointers the kernels were given.
+struct GraphKey {
+    int64_t v[20];
+    bool operator<(const GraphKey &o) const
+    {
+        return std::lexicographical_compare(v, v + 20, o.v, o.v + 20);
+    }
+};
+std::map<GraphKey, hipGraphExec_t> g_graphs;
+
+void drop_graphs()
+{
+    for (auto &kv : g_graphs) (void)hipGraphExecDestroy(kv.second);
+    g_graphs.clear();
+}
+
 rrs_status ensure_arena(int dev, size_t need, void **out)
 {
     Arena &a = g_arenas[dev];
     if (a.cap < need) {
+        drop_graphs();  // they point into the arena
         if (a.base) {
             RRS_HIP_TRY(hipDeviceSynchronize());
             RRS_HIP_TRY(hipFree(a.base));
@@ -83,6 +102,10 @@ rrs_status run(int notion, const double *X, int64_t n, int64_t d, const double *
     rrs_status vs = rrs::job_validate(s, n, d);
     if (vs != RRS_OK) return vs;
     const bool dev_ptrs = o.device_ptrs != 0;
+    if (o.reserved != 0 || (o.flags & ~RRS_FLAG_GRAPH) != 0)
+        return fail(RRS_E_INVAL, "unknown flags or non-zero reserved field in opts");
+    if ((o.flags & RRS_FLAG_GRAPH) && (!dev_ptrs || o.stream == nullptr))
+        return fail(RRS_E_INVAL, "RRS_FLAG_GRAPH needs device pointers and a non-default stream");
     if (!dev_ptrs) {
         if (!all_finite(X, n * d)) return fail(RRS_E_INVAL, "X holds a non-finite value");
         if (!all_finite(Z, nq * d)) return fail(RRS_E_INVAL, "Z holds a non-finite value");
@@ -148,8 +171,45 @@ rrs_status run(int notion, const double *X, int64_t n, int64_t d, const double *
     D.X = Xd;
     D.n = n;
     D.d = d;
-    RRS_HIP_TRY(rrs::data_prepare(D, data_mem, plan.prec, st));
     uint32_t *stats = nullptr;
+    if ((o.flags & RRS_FLAG_GRAPH) && !g_prof.on) {
+        // the whole device side as one graph: captured on first use, then replayed
+        GraphKey key{};
+        int64_t *v = key.v;
+        double abits = alpha;
+        int64_t ab;
+        std::memcpy(&ab, &abits, sizeof(ab));
+        const int64_t vals[20] = {notion, o.precision, n, d, nq, K, r, ab, (int64_t)seed,
+                                  o.query_offset, (int64_t)X, (int64_t)Z, (int64_t)depth,
+                                  (int64_t)count, (int64_t)o.poles, (int64_t)o.trace,
+                                  (int64_t)st, (int64_t)base, (int64_t)plan.qb, dev};
+        std::memcpy(v, vals, sizeof(vals));
+        auto it = g_graphs.find(key);
+        if (it == g_graphs.end()) {
+            RRS_HIP_TRY(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+            hipError_t pe = rrs::data_prepare(D, data_mem, plan.prec, st);
+            rrs_status es = pe == hipSuccess
+                                ? rrs::enqueue_job(s, D, plan, io, ws, st, nullptr, nullptr)
+                                : fail(RRS_E_DEVICE, "data preparation failed: %s",
+                                       hipGetErrorString(pe));
+            hipGraph_t graph = nullptr;
+            const hipError_t ce = hipStreamEndCapture(st, &graph);
+            if (es != RRS_OK) {
+                if (graph) (void)hipGraphDestroy(graph);
+                return es;
+            }
+            RRS_HIP_TRY(ce);
+            hipGraphExec_t exec = nullptr;
+            const hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(graph);
+            RRS_HIP_TRY(ie);
+            it = g_graphs.emplace(key, exec).first;
+        }
+        RRS_HIP_TRY(hipGraphLaunch(it->second, st));
+        RRS_HIP_TRY(hipStreamSynchronize(st));
+        return RRS_OK;
+    }
+    RRS_HIP_TRY(rrs::data_prepare(D, data_mem, plan.prec, st));
     rrs_status es = rrs::enqueue_job(s, D, plan, io, ws, st, &g_prof, &stats);
     if (es != RRS_OK) return es;
     if (stage_in) {
@@ -211,6 +271,7 @@ const char *rrs_last_error(void) { return rrs::last_error().c_str(); }
 rrs_status rrs_release_workspace(void)
 {
     std::lock_guard<std::mutex> lock(g_mutex);
+    drop_graphs();
     int cur = 0;
     if (hipGetDevice(&cur) != hipSuccess) cur = 0;
     for (auto &kv : g_arenas) {

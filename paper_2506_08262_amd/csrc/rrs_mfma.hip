@@ -18,6 +18,12 @@
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdint.h>
+#include <stdio.h>
+#include <stdlib.h>
+
+#include <map>
+#include <mutex>
+#include <tuple>
 
 #include "rrs_launch.hpp"
 
@@ -219,8 +225,157 @@ struct GemmLds {
 
 enum { EPI_SIGN = 0, EPI_STORE = 1 };
 
+// the chunk-prefetch variant stages a B chunk with at most 8 pieces per thread
+static_assert(kTN * (kKC / 8) * 2 <= 256 * 8, "bf16 B chunk exceeds the staging registers");
+static_assert(kTN * (kKC / 4) <= 256 * 8, "binary32 B chunk exceeds the staging registers");
+
+// Variant 1 (chunk prefetch): per K chunk the B rows go global -> registers
+// -> LDS and every A fragment of the chunk is requested before the first
+// MFMA, so the global latencies of both overlap and are paid once per chunk
+// (more registers, fewer waves per SIMD).
 template <int PREC>
-__device__ __forceinline__ void gemm_block(const void *__restrict__ A0,
+__device__ __forceinline__ void gemm_block_chunk(const void *__restrict__ A0,
+                                           const void *__restrict__ A1, int64_t n, int64_t kp,
+                                           const void *__restrict__ B0,
+                                           const void *__restrict__ B1, int64_t J0,
+                                           int64_t row0, GemmLds &L, f32x16 (&acc)[2][4])
+{
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int lr = lane & 31, lh = lane >> 5;
+#pragma unroll
+    for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+        for (int ct = 0; ct < 4; ++ct)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) acc[rt][ct][r] = 0.0f;
+    int64_t ar[2];
+#pragma unroll
+    for (int rt = 0; rt < 2; ++rt) {
+        ar[rt] = row0 + rt * 32 + lr;
+        if (ar[rt] > n - 1) ar[rt] = n - 1;  // clamp; rows >= n are ignored
+    }
+    constexpr int kStep = PREC == MFMA_BF16 ? 16 : 8;   // K per MFMA group
+    constexpr int kSteps = kKC / kStep;                  // groups per full chunk
+    for (int64_t k0 = 0; k0 < kp; k0 += kKC) {
+        const int kc = (int)((kp - k0) < kKC ? (kp - k0) : kKC);
+        const int ns = kc / kStep;
+        if (PREC == MFMA_BF16) {
+            // B chunk: 128 rows x kc, two terms, 16-byte pieces (<= 8 per thread)
+            const int per_row = kc / 8;
+            const int total = kTN * per_row * 2;
+            bf16x8 bst[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int p = tid + 256 * u;
+                if (p < total) {
+                    const int term = p / (kTN * per_row);
+                    const int q = p - term * kTN * per_row;
+                    const int row = q / per_row, piece = q - row * per_row;
+                    bst[u] = *(const bf16x8 *)((const __bf16 *)(term ? B1 : B0) +
+                                               (J0 + row) * kp + k0 + piece * 8);
+                }
+            }
+            bf16x8 ah[kSteps][2], al[kSteps][2];
+#pragma unroll
+            for (int st = 0; st < kSteps; ++st)
+                if (st < ns)
+#pragma unroll
+                    for (int rt = 0; rt < 2; ++rt) {
+                        const int64_t off = ar[rt] * kp + k0 + st * 16 + 8 * lh;
+                        ah[st][rt] = *(const bf16x8 *)((const __bf16 *)A0 + off);
+                        al[st][rt] = *(const bf16x8 *)((const __bf16 *)A1 + off);
+                    }
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int p = tid + 256 * u;
+                if (p < total) {
+                    const int term = p / (kTN * per_row);
+                    const int q = p - term * kTN * per_row;
+                    const int row = q / per_row, piece = q - row * per_row;
+                    *(bf16x8 *)(L.bh + (term * kTN + row) * kLdsRow16 + piece * 8) = bst[u];
+                }
+            }
+            __syncthreads();
+#pragma unroll
+            for (int st = 0; st < kSteps; ++st) {
+                if (st >= ns) break;
+#pragma unroll
+                for (int ct = 0; ct < 4; ++ct) {
+                    const int col = ct * 32 + lr;
+                    const bf16x8 bh =
+                        *(const bf16x8 *)(L.bh + col * kLdsRow16 + st * 16 + 8 * lh);
+                    const bf16x8 bl =
+                        *(const bf16x8 *)(L.bh + (kTN + col) * kLdsRow16 + st * 16 + 8 * lh);
+#pragma unroll
+                    for (int rt = 0; rt < 2; ++rt) {
+                        acc[rt][ct] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
+                            ah[st][rt], bh, acc[rt][ct], 0, 0, 0);
+                        acc[rt][ct] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
+                            ah[st][rt], bl, acc[rt][ct], 0, 0, 0);
+                        acc[rt][ct] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
+                            al[st][rt], bh, acc[rt][ct], 0, 0, 0);
+                    }
+                }
+            }
+        } else {
+            const int per_row = kc / 4;
+            const int total = kTN * per_row;
+            f32x4 bst[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int p = tid + 256 * u;
+                if (p < total) {
+                    const int row = p / per_row, piece = p - row * per_row;
+                    bst[u] = *(const f32x4 *)((const float *)B0 + (J0 + row) * kp + k0 +
+                                              piece * 4);
+                }
+            }
+            f32x4 a[kSteps][2];
+#pragma unroll
+            for (int st = 0; st < kSteps; ++st)
+                if (st < ns)
+#pragma unroll
+                    for (int rt = 0; rt < 2; ++rt)
+                        a[st][rt] = *(const f32x4 *)((const float *)A0 + ar[rt] * kp + k0 +
+                                                     st * 8 + 4 * lh);
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int p = tid + 256 * u;
+                if (p < total) {
+                    const int row = p / per_row, piece = p - row * per_row;
+                    *(f32x4 *)(L.bf + row * kLdsRow32 + piece * 4) = bst[u];
+                }
+            }
+            __syncthreads();
+#pragma unroll
+            for (int st = 0; st < kSteps; ++st) {
+                if (st >= ns) break;
+#pragma unroll
+                for (int ct = 0; ct < 4; ++ct) {
+                    const int col = ct * 32 + lr;
+                    const f32x4 b = *(const f32x4 *)(L.bf + col * kLdsRow32 + st * 8 + 4 * lh);
+#pragma unroll
+                    for (int rt = 0; rt < 2; ++rt) {
+                        acc[rt][ct] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[st][rt][0], b[0],
+                                                                           acc[rt][ct], 0, 0, 0);
+                        acc[rt][ct] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[st][rt][1], b[1],
+                                                                           acc[rt][ct], 0, 0, 0);
+                        acc[rt][ct] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[st][rt][2], b[2],
+                                                                           acc[rt][ct], 0, 0, 0);
+                        acc[rt][ct] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[st][rt][3], b[3],
+                                                                           acc[rt][ct], 0, 0, 0);
+                    }
+                }
+            }
+        }
+        __syncthreads();  // the next chunk overwrites the staged B
+    }
+}
+
+// Variant 0 (per-step loads): B chunks staged through LDS, A fragments
+// loaded right before the MFMAs of each K step (fewer registers).
+template <int PREC>
+__device__ __forceinline__ void gemm_block_steps(const void *__restrict__ A0,
                                            const void *__restrict__ A1, int64_t n, int64_t kp,
                                            const void *__restrict__ B0,
                                            const void *__restrict__ B1, int64_t J0,
@@ -316,7 +471,7 @@ __device__ __forceinline__ void gemm_block(const void *__restrict__ A0,
     }
 }
 
-template <int PREC, int EPI>
+template <int PREC, int EPI, int PF>
 __global__ __launch_bounds__(256) void k_gemm(
     const void *__restrict__ A0, const void *__restrict__ A1,
     const float *__restrict__ anorm, int64_t n, int64_t kp,
@@ -335,7 +490,11 @@ __global__ __launch_bounds__(256) void k_gemm(
         L.an[tid] = i < n ? anorm[i] : 0.0f;
     }
     f32x16 acc[2][4];
-    gemm_block<PREC>(A0, A1, n, kp, B0, B1, J0, row0, L, acc);  // its barriers publish L.an
+    // the block's barriers publish L.an
+    if (PF)
+        gemm_block_chunk<PREC>(A0, A1, n, kp, B0, B1, J0, row0, L, acc);
+    else
+        gemm_block_steps<PREC>(A0, A1, n, kp, B0, B1, J0, row0, L, acc);
 
     if (EPI == EPI_STORE) {
         // S[J][i]: lane lr writes rows (r / 4) 8 + 4 lh .. + 3 of column J
@@ -561,46 +720,231 @@ hipError_t launch_mfma_dirs(int prec, bool fold, const double *UT, int64_t d, in
 
 int64_t mfma_col_pad(int64_t ncols) { return (ncols + kTN - 1) / kTN * kTN; }
 
+namespace {
+
+constexpr int kVariants = 2;
+
+// Launch of one GEMM variant (PF = variant) for either epilogue.
+struct GemmLaunch {
+    int prec, epi;
+    dim3 grid;
+    const void *A0, *A1;
+    const float *anorm;
+    int64_t n, kp;
+    const void *B0, *B1;
+    const float *cmarg;
+    int64_t m, ncols, ldm;
+    float kappa_a;
+    uint32_t *cnt;
+    uint64_t *queue;
+    uint32_t *qcount;
+    uint64_t qcap;
+    float *S;
+
+    template <int P, int E, int V>
+    void go(hipStream_t st) const
+    {
+        hipLaunchKernelGGL((k_gemm<P, E, V>), grid, dim3(256), 0, st, A0, A1, anorm, n, kp, B0,
+                           B1, cmarg, m, ncols, ldm, kappa_a, cnt, queue, qcount, qcap, S);
+    }
+    template <int V>
+    void go_v(hipStream_t st) const
+    {
+        if (epi == EPI_STORE) {
+            if (prec == MFMA_BF16)
+                go<MFMA_BF16, EPI_STORE, V>(st);
+            else
+                go<MFMA_F32, EPI_STORE, V>(st);
+        } else if (prec == MFMA_BF16) {
+            go<MFMA_BF16, EPI_SIGN, V>(st);
+        } else if (prec == MFMA_F32) {
+            go<MFMA_F32, EPI_SIGN, V>(st);
+        } else {
+            go<MFMA_F32_PLAIN, EPI_SIGN, V>(st);
+        }
+    }
+    hipError_t run(int v, hipStream_t st) const
+    {
+        if (v == 1)
+            go_v<1>(st);
+        else
+            go_v<0>(st);
+        return hipGetLastError();
+    }
+};
+
+// ---------------------------------------------------------------------------
+// Autotuner.  The variant of a GEMM launch is chosen per key (epilogue,
+// format, padded K, log2 buckets of n and of the column count) by timing
+// every variant on the first launch with that key, on that launch's own
+// operands (the sign epilogue's counters and queue are cleared after each
+// trial, so the launch that follows starts from zero as usual).  Choices are
+// kept for the process; with RRS_TUNE_CACHE=<file> they are also read from
+// and appended to that file (lines: epi prec kp nbucket cbucket variant).
+// RRS_TUNE=0 turns timing off (variant 0), RRS_TUNE=v+1 forces variant v.
+// A stream under graph capture is never timed.
+// ---------------------------------------------------------------------------
+struct TuneKey {
+    int epi, prec;
+    int64_t kp;
+    int nb, cb;
+    bool operator<(const TuneKey &o) const
+    {
+        return std::tie(epi, prec, kp, nb, cb) < std::tie(o.epi, o.prec, o.kp, o.nb, o.cb);
+    }
+};
+std::mutex g_tune_mu;
+std::map<TuneKey, int> g_tune;
+bool g_tune_loaded = false;
+
+int log2_bucket(int64_t x)
+{
+    int b = 0;
+    while (x > 1) {
+        x >>= 1;
+        ++b;
+    }
+    return b;
+}
+
+int tune_mode()
+{
+    const char *e = getenv("RRS_TUNE");
+    if (!e || !*e) return -1;  // tune
+    return atoi(e);            // 0: off, v + 1: force v
+}
+
+void tune_load_locked()
+{
+    if (g_tune_loaded) return;
+    g_tune_loaded = true;
+    const char *path = getenv("RRS_TUNE_CACHE");
+    if (!path || !*path) return;
+    FILE *f = fopen(path, "r");
+    if (!f) return;
+    TuneKey k;
+    long long kp;
+    int v;
+    while (fscanf(f, "%d %d %lld %d %d %d", &k.epi, &k.prec, &kp, &k.nb, &k.cb, &v) == 6) {
+        k.kp = kp;
+        if (v >= 0 && v < kVariants) g_tune[k] = v;
+    }
+    fclose(f);
+}
+
+void tune_store_locked(const TuneKey &k, int v)
+{
+    g_tune[k] = v;
+    const char *path = getenv("RRS_TUNE_CACHE");
+    if (!path || !*path) return;
+    FILE *f = fopen(path, "a");
+    if (!f) return;
+    fprintf(f, "%d %d %lld %d %d %d\n", k.epi, k.prec, (long long)k.kp, k.nb, k.cb, v);
+    fclose(f);
+}
+
+hipError_t tuned_launch(const GemmLaunch &g, int64_t cnt_words, hipStream_t st)
+{
+    const int mode = tune_mode();
+    if (mode >= 0) return g.run(mode == 0 ? 0 : (mode - 1) % kVariants, st);
+    const TuneKey key{g.epi, g.prec, g.kp, log2_bucket(g.n), log2_bucket(g.ncols)};
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        tune_load_locked();
+        auto it = g_tune.find(key);
+        if (it != g_tune.end()) return g.run(it->second, st);
+    }
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(st, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone)
+        return g.run(0, st);
+    hipEvent_t ev[2];
+    if (hipEventCreate(&ev[0]) != hipSuccess) return g.run(0, st);
+    if (hipEventCreate(&ev[1]) != hipSuccess) {
+        (void)hipEventDestroy(ev[0]);
+        return g.run(0, st);
+    }
+    float best_ms = 0.f;
+    int best = 0;
+    hipError_t e = hipSuccess;
+    for (int v = 0; v < kVariants && e == hipSuccess; ++v) {
+        float ms = 0.f;
+        for (int rep = 0; rep < 2 && e == hipSuccess; ++rep) {  // the first loads the code
+            e = hipEventRecord(ev[0], st);
+            if (e == hipSuccess) e = g.run(v, st);
+            if (e == hipSuccess) e = hipEventRecord(ev[1], st);
+            if (e == hipSuccess) e = hipEventSynchronize(ev[1]);
+            if (e == hipSuccess) e = hipEventElapsedTime(&ms, ev[0], ev[1]);
+        }
+        if (e == hipSuccess && (v == 0 || ms < best_ms)) {
+            best_ms = ms;
+            best = v;
+        }
+    }
+    (void)hipEventDestroy(ev[0]);
+    (void)hipEventDestroy(ev[1]);
+    if (e != hipSuccess) return e;
+    if (g.epi == EPI_SIGN) {
+        // trials accumulated into the counters and the queue: start over
+        e = launch_fill_u32(g.cnt, cnt_words, 0u, st);
+        if (e == hipSuccess) e = launch_fill_u32(g.qcount, 2, 0u, st);
+        if (e != hipSuccess) return e;
+    }
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        tune_store_locked(key, best);
+    }
+    return g.run(best, st);
+}
+
+}  // namespace
+
 hipError_t launch_mfma_store(int prec, const void *A0, const void *A1, int64_t n, int64_t d,
                              const void *B0, const void *B1, int64_t m, int64_t ncols,
                              int64_t npad, float *S, hipStream_t st)
 {
-    const int64_t kp = mfma_kpad(prec, d);
-    dim3 grid((unsigned)((ncols + kTN - 1) / kTN), (unsigned)((n + kTM - 1) / kTM));
-    if (npad < (int64_t)grid.x * kTN) return hipErrorInvalidValue;
-#define RRS_STORE(P)                                                                          \
-    hipLaunchKernelGGL((k_gemm<P, EPI_STORE>), grid, dim3(256), 0, st, A0, A1, nullptr, n, kp, \
-                       B0, B1, nullptr, m, ncols, (int64_t)0, 0.0f, nullptr, nullptr, nullptr, \
-                       (uint64_t)0, S)
-    if (prec == MFMA_BF16)
-        RRS_STORE(MFMA_BF16);
-    else
-        RRS_STORE(MFMA_F32);
-#undef RRS_STORE
-    return hipGetLastError();
+    GemmLaunch g{};
+    g.prec = prec == MFMA_BF16 ? MFMA_BF16 : MFMA_F32;
+    g.epi = EPI_STORE;
+    g.kp = mfma_kpad(prec, d);
+    g.grid = dim3((unsigned)((ncols + kTN - 1) / kTN), (unsigned)((n + kTM - 1) / kTM));
+    if (npad < (int64_t)g.grid.x * kTN) return hipErrorInvalidValue;
+    g.A0 = A0;
+    g.A1 = A1;
+    g.n = n;
+    g.B0 = B0;
+    g.B1 = B1;
+    g.m = m;
+    g.ncols = ncols;
+    g.S = S;
+    return tuned_launch(g, 0, st);
 }
 
 hipError_t launch_mfma_gemm(const MfmaArgs &a, hipStream_t st)
 {
     double kappa, canon;
-    const int64_t kp = mfma_kpad(a.prec, a.d);
-    mfma_margins(a.prec, a.d, kp, &kappa, &canon);
-    const float kappa_a = (float)((kappa + canon) * 1.000001);
-    const int64_t ncols = a.qb * a.m;
-    dim3 grid((unsigned)((ncols + kTN - 1) / kTN), (unsigned)((a.n + kTM - 1) / kTM));
-    if (a.npad < (int64_t)grid.x * kTN) return hipErrorInvalidValue;
-#define RRS_GEMM(P)                                                                           \
-    hipLaunchKernelGGL((k_gemm<P, EPI_SIGN>), grid, dim3(256), 0, st, a.A0, a.A1, a.anorm, a.n, \
-                       kp, a.B0, a.B1, a.cmarg, a.m, ncols, a.ldm, kappa_a, a.cnt, a.queue,    \
-                       a.qcount, a.qcap, nullptr)
-    if (a.prec == MFMA_BF16)
-        RRS_GEMM(MFMA_BF16);
-    else if (a.prec == MFMA_F32)
-        RRS_GEMM(MFMA_F32);
-    else
-        RRS_GEMM(MFMA_F32_PLAIN);
-#undef RRS_GEMM
-    return hipGetLastError();
+    GemmLaunch g{};
+    g.prec = a.prec;
+    g.epi = EPI_SIGN;
+    g.kp = mfma_kpad(a.prec, a.d);
+    mfma_margins(a.prec, a.d, g.kp, &kappa, &canon);
+    g.kappa_a = (float)((kappa + canon) * 1.000001);
+    g.ncols = a.qb * a.m;
+    g.grid = dim3((unsigned)((g.ncols + kTN - 1) / kTN), (unsigned)((a.n + kTM - 1) / kTM));
+    if (a.npad < (int64_t)g.grid.x * kTN) return hipErrorInvalidValue;
+    g.A0 = a.A0;
+    g.A1 = a.A1;
+    g.anorm = a.anorm;
+    g.n = a.n;
+    g.B0 = a.B0;
+    g.B1 = a.B1;
+    g.cmarg = a.cmarg;
+    g.m = a.m;
+    g.ldm = a.ldm;
+    g.cnt = a.cnt;
+    g.queue = a.queue;
+    g.qcount = a.qcount;
+    g.qcap = a.qcap;
+    return tuned_launch(g, a.qb * a.ldm * 2, st);
 }
 
 hipError_t launch_mfma_recheck(const MfmaArgs &a, hipStream_t st)

@@ -47,12 +47,13 @@ constexpr int kBins = 256;
 constexpr int kCapW = 512;       // candidates of one window
 constexpr int kRadixCand = 64;
 constexpr int kUnroll = 4;
+constexpr int kDs = 128;         // coordinates kept in LDS for the recomputation
 
 struct RcShared {
     uint32_t hist[kBins + 64];   // 256 bins, then one dummy slot per lane
     uint32_t skey[64];
     uint32_t srank[64];
-    double sval[64];
+    float sval[64];
     uint32_t cidx[kCapW];
     double cval[kCapW];
     uint32_t Lk, R, sh, tau;
@@ -65,6 +66,7 @@ struct RcShared {
     uint64_t rcand[kRadixCand];
     uint32_t nrcand;
     uint64_t rresult, minkey;
+    double zs[kDs], us[kDs];   // the column's query and direction (d <= kDs)
 };
 
 // One column and what its exact recomputation needs.
@@ -74,27 +76,76 @@ struct Col {
     double c, E;
     const double *X;   // [n][d]
     int64_t d;
-    const double *z;   // [d]
-    const double *u;   // direction j: u[c * ldm]
-    int64_t ldm;
+    const double *z;   // [d] query (LDS copy when d <= kDs)
+    const double *u;   // [d] direction j, unit stride (LDS copy when d <= kDs)
+    int64_t ustride;   // stride of u: 1 for the LDS copy, ldm in global memory
 };
 
 // The recipe's projection of point i (EXACT), or the binary32 one shifted.
+// The loads of four coordinates are issued before their fma steps; the fma
+// chain itself keeps the recipe's coordinate order.
 template <bool EXACT>
 __device__ __forceinline__ double exact_t(const Col &C, int64_t i)
 {
     if (!EXACT) return (double)C.s[i] - C.c;
     const double *x = C.X + i * C.d;
+    const double *z = C.z, *u = C.u;
+    const int64_t us = C.ustride, d = C.d;
     double t = 0.0;
-    for (int64_t c = 0; c < C.d; ++c) t = fma(x[c] - C.z[c], C.u[c * C.ldm], t);
+    int64_t c = 0;
+    for (; c + 4 <= d; c += 4) {
+        const double x0 = x[c], x1 = x[c + 1], x2 = x[c + 2], x3 = x[c + 3];
+        t = fma(x0 - z[c], u[c * us], t);
+        t = fma(x1 - z[c + 1], u[(c + 1) * us], t);
+        t = fma(x2 - z[c + 2], u[(c + 2) * us], t);
+        t = fma(x3 - z[c + 3], u[(c + 3) * us], t);
+    }
+    for (; c < d; ++c) t = fma(x[c] - z[c], u[c * us], t);
     return t;
 }
 
-// Approximation of point i's value in phase PH (0: s_i; 1: |s_i - sig|).
+// Approximation of point i's value in phase PH, in binary32 (0: s_i;
+// 1: |s_i - sig|, sig rounded to binary32).
 template <int PH>
-__device__ __forceinline__ double approx_v(double s, double sig)
+__device__ __forceinline__ float approx_v(float s, float sig)
 {
-    return PH == 0 ? s : fabs(s - sig);
+    return PH == 0 ? s : fabsf(s - sig);
+}
+
+// Order key of a binary32 value in phase PH (phase 0 values carry a sign,
+// phase 1 values are >= 0); finite values only take part.
+template <int PH>
+__device__ __forceinline__ uint32_t fkey32(float x)
+{
+    const uint32_t b = __float_as_uint(x);
+    if (PH == 0) return b ^ ((uint32_t)((int32_t)b >> 31) | 0x80000000u);
+    return b;
+}
+
+template <int PH>
+__device__ __forceinline__ bool fkey_finite(uint32_t k)
+{
+    return PH == 0 ? k < 0xFF800000u : k < 0x7F800000u;
+}
+
+// Bracket key on binary32 bits with magnitudes below tau collapsed onto the
+// key of zero (as bin_key does on binary64 high words); monotone in x.
+template <int PH>
+__device__ __forceinline__ uint32_t fbin_key(float x, uint32_t tau)
+{
+    const uint32_t b = __float_as_uint(x);
+    const uint32_t mag = b & 0x7FFFFFFFu;
+    const uint32_t dd = mag - tau;
+    if (PH == 0) {
+        if (mag < tau) return 0x80000000u;
+        return (b >> 31) ? 0x7FFFFFFFu - dd : 0x80000001u + dd;
+    }
+    return mag < tau ? 0u : 1u + dd;
+}
+
+__device__ __forceinline__ float lane_bcast_f(float x, int src)
+{
+    return __uint_as_float((uint32_t)__builtin_amdgcn_readlane((int)__float_as_uint(x), src));
 }
 
 // Exact value in phase PH from the exact projection t.
@@ -104,29 +155,31 @@ __device__ __forceinline__ double exact_v(double t, double med)
     return PH == 0 ? t : fabs(t - med);
 }
 
-__device__ __forceinline__ double hi_to_double(uint32_t hi) { return __hiloint2double((int)hi, 0); }
+__device__ __forceinline__ double bits_value(uint32_t b) { return (double)__uint_as_float(b); }
 
-// Bounds of the values whose bin_key<PH>(., tau) is K: lo <= x <= hi.
+// Bounds of the binary32 values whose fbin_key<PH>(., tau) is K: every key
+// outside the collapsed neighbourhood of zero is one value, the collapsed key
+// holds the magnitudes below tau.
 template <int PH>
 __device__ __forceinline__ double key_lo_value(uint32_t K, uint32_t tau)
 {
     if (PH == 0) {
-        if (K > 0x80000000u) return hi_to_double(K - 0x80000001u + tau);
-        if (K == 0x80000000u) return -hi_to_double(tau);
-        return -hi_to_double(0x7FFFFFFFu - K + tau + 1u);
+        if (K > 0x80000000u) return bits_value(K - 0x80000001u + tau);
+        if (K == 0x80000000u) return -bits_value(tau);
+        return -bits_value(0x7FFFFFFFu - K + tau);
     }
-    return K == 0u ? 0.0 : hi_to_double(K - 1u + tau);
+    return K == 0u ? 0.0 : bits_value(K - 1u + tau);
 }
 
 template <int PH>
 __device__ __forceinline__ double key_hi_value(uint32_t K, uint32_t tau)
 {
     if (PH == 0) {
-        if (K > 0x80000000u) return hi_to_double(K - 0x80000001u + tau + 1u);
-        if (K == 0x80000000u) return hi_to_double(tau);
-        return -hi_to_double(0x7FFFFFFFu - K + tau);
+        if (K > 0x80000000u) return bits_value(K - 0x80000001u + tau);
+        if (K == 0x80000000u) return bits_value(tau);
+        return -bits_value(0x7FFFFFFFu - K + tau);
     }
-    return K == 0u ? hi_to_double(tau) : hi_to_double(K + tau);
+    return K == 0u ? bits_value(tau) : bits_value(K - 1u + tau);
 }
 
 // Where a select reads the column's binary32 projections from.
@@ -290,6 +343,7 @@ __device__ bool rc_select(const Col &C, const SRC &src, double med, double sig, 
 {
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int64_t n = C.n;
+    const float sigf = (float)sig;
     sh.hist[tid] = 0;
     if (tid < 64) sh.srank[tid] = 0;
     if (tid == 0) {
@@ -299,9 +353,9 @@ __device__ bool rc_select(const Col &C, const SRC &src, double med, double sig, 
     // 64 sampled approximations: slot 16 w + l from lane l < 16 of wave w
     if (lane < 16) {
         const int slot = wave * 16 + lane;
-        const double x = approx_v<PH>((double)src.sample(slot), sig);
-        const uint32_t kx = key32<PH>(x);
-        sh.skey[slot] = key_takes_part<PH>(kx) ? kx : 0xFFFFFFFFu;
+        const float x = approx_v<PH>(src.sample(slot), sigf);
+        const uint32_t kx = fkey32<PH>(x);
+        sh.skey[slot] = fkey_finite<PH>(kx) ? kx : 0xFFFFFFFFu;
         sh.sval[slot] = x;
     }
     __syncthreads();
@@ -333,12 +387,12 @@ __device__ bool rc_select(const Col &C, const SRC &src, double med, double sig, 
             if (hi > (double)(S - 1)) hi = (double)(S - 1);
             const uint32_t rlo = (uint32_t)lo, rhi = (uint32_t)hi;
             const uint64_t mlo = __ballot(ok && rank == rlo), mhi = __ballot(ok && rank == rhi);
-            const double xv = sh.sval[lane];
-            const double L = lane_bcast(xv, __ffsll((long long)mlo) - 1);
-            const double H = lane_bcast(xv, __ffsll((long long)mhi) - 1);
-            tau = (uint32_t)__double2hiint(fmax(fabs(L), fabs(H)) * 0x1p-6) & 0x7FFFFFFFu;
-            Lk = bin_key<PH>(L, tau);
-            Hk = bin_key<PH>(H, tau);
+            const float xv = sh.sval[lane];
+            const float L = lane_bcast_f(xv, __ffsll((long long)mlo) - 1);
+            const float H = lane_bcast_f(xv, __ffsll((long long)mhi) - 1);
+            tau = __float_as_uint(fmaxf(fabsf(L), fabsf(H)) * 0x1p-6f) & 0x7FFFFFFFu;
+            Lk = fbin_key<PH>(L, tau);
+            Hk = fbin_key<PH>(H, tau);
         }
         if (lane == 0) {
             const uint32_t R = Hk - Lk;
@@ -357,7 +411,7 @@ __device__ bool rc_select(const Col &C, const SRC &src, double med, double sig, 
         uint32_t nbelow = 0;
         const uint32_t dummy = (uint32_t)kBins + (uint32_t)lane;
         src.each([&](int64_t, float sv, bool live) {
-            const uint32_t kx = bin_key<PH>(approx_v<PH>((double)sv, sig), tau);
+            const uint32_t kx = fbin_key<PH>(approx_v<PH>(sv, sigf), tau);
             const uint32_t dk = kx - Lk;
             nbelow += (live && kx < Lk) ? 1u : 0u;
             atomicAdd(&sh.hist[(live && dk <= R) ? (dk >> bsh) : dummy], 1u);
@@ -386,15 +440,17 @@ __device__ bool rc_select(const Col &C, const SRC &src, double med, double sig, 
             if (khi > (uint64_t)Lk + R) khi = (uint64_t)Lk + R;
             const double vlo = key_lo_value<PH>((uint32_t)klo, tau);
             const double vhi = key_hi_value<PH>((uint32_t)khi, tau);
-            // phase 1 adds the rounding of s - sig (binary64) to the bound
-            const double Ew = PH == 0 ? E : E * 1.000001 + 0x1p-48 * (fabs(sig) + fabs(vlo) +
-                                                                      fabs(vhi) + E);
-            const double wlo = vlo - 2.0 * Ew, whi = vhi + 2.0 * Ew;
+            // phase 1 adds the roundings of sig to binary32 and of s - sig
+            const double Ew = PH == 0 ? E : E * 1.000001 + 0x1p-22 * (fabs(sig) + fabs(vlo) +
+                                                                      fabs(vhi) + E) + 1e-300;
+            // the window, rounded outwards to binary32
+            const float wlo = __double2float_rd(vlo - 2.0 * Ew);
+            const float whi = __double2float_ru(vhi + 2.0 * Ew);
             if (tid == 0) sh.below = 0;
             __syncthreads();
             nbelow = 0;
             src.each([&](int64_t i, float sv, bool live) {
-                const double x = approx_v<PH>((double)sv, sig);
+                const float x = approx_v<PH>(sv, sigf);
                 nbelow += (live && x < wlo) ? 1u : 0u;
                 if (live && x >= wlo && x <= whi) {
                     const uint32_t p = atomicAdd(&sh.ncand, 1u);
@@ -524,9 +580,20 @@ __global__ __launch_bounds__(kT) void k_select_rc(const float *__restrict__ S, i
     C.E = EXACT ? eq[qi * m + j] : 0.0;
     C.X = X;
     C.d = d;
-    C.z = Zb + qi * d;
-    C.u = UT + qi * d * ldm + j;
-    C.ldm = ldm;
+    if (EXACT && d <= kDs) {
+        for (int64_t c = threadIdx.x; c < d; c += kT) {
+            sh.zs[c] = Zb[qi * d + c];
+            sh.us[c] = UT[qi * d * ldm + c * ldm + j];
+        }
+        __syncthreads();
+        C.z = sh.zs;
+        C.u = sh.us;
+        C.ustride = 1;
+    } else {
+        C.z = Zb + qi * d;
+        C.u = UT + qi * d * ldm + j;
+        C.ustride = ldm;
+    }
     double D;
     if (VPT == 0) {
         D = rc_depth<NOTION, EXACT>(C, StreamSrc{C.s, n}, sh, stats);

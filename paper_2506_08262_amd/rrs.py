@@ -17,6 +17,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "librrs.so")
 
 RRS_OK, RRS_E_INVAL, RRS_E_NOMEM, RRS_E_DEVICE = 0, 1, 2, 3
+RRS_FLAG_GRAPH = 1
 RRS_E_BUSY, RRS_E_CANCELLED, RRS_E_INTERNAL = 4, 5, 6
 RRS_F64, RRS_F32_RECHECK, RRS_BF16_RECHECK, RRS_F32_PLAIN = 0, 1, 2, 3
 PRECISIONS = {"f64": RRS_F64, "f32": RRS_F32_RECHECK, "bf16": RRS_BF16_RECHECK,
@@ -45,7 +46,9 @@ class rrs_opts(ctypes.Structure):
                 ("query_offset", ctypes.c_int64),
                 ("poles", ctypes.c_void_p),
                 ("trace", ctypes.c_void_p),
-                ("workspace_limit", ctypes.c_size_t)]
+                ("workspace_limit", ctypes.c_size_t),
+                ("flags", ctypes.c_uint32),
+                ("reserved", ctypes.c_uint32)]
 
 
 class rrs_kernel_stat(ctypes.Structure):
@@ -170,7 +173,7 @@ def _alloc_like(X, shape, np_dtype, torch_dtype):
 
 
 def _run(fn_name, X, Z, K, n_refine, cap_shrink, seed, precision, query_offset,
-         want_count, want_poles, want_trace, stream, workspace_limit):
+         want_count, want_poles, want_trace, stream, workspace_limit, graph=False):
     import_torch = _is_torch(X) or _is_torch(Z)
     f64 = (np.float64, None)
     i64 = (np.int64, None)
@@ -212,6 +215,7 @@ def _run(fn_name, X, Z, K, n_refine, cap_shrink, seed, precision, query_offset,
     o.poles = ptr(poles)
     o.trace = ptr(trace)
     o.workspace_limit = int(workspace_limit or 0)
+    o.flags = RRS_FLAG_GRAPH if graph else 0
     L = load()
     args = [Xp, n, d, Zp, nq, int(K), int(n_refine), float(cap_shrink), int(seed), ptr(depth)]
     if fn_name == "rrs_depth_halfspace":
@@ -229,24 +233,27 @@ def _run(fn_name, X, Z, K, n_refine, cap_shrink, seed, precision, query_offset,
 
 
 def rrs_depth_halfspace(X, Z, K, n_refine, cap_shrink, seed=0, precision="f64", query_offset=0,
-                        want_poles=False, want_trace=False, stream=None, workspace_limit=0):
+                        want_poles=False, want_trace=False, stream=None, workspace_limit=0,
+                        graph=False):
     """Halfspace depth of each row of Z; returns dict(depth, count[, poles, trace])."""
     return _run("rrs_depth_halfspace", X, Z, K, n_refine, cap_shrink, seed, precision,
-                query_offset, True, want_poles, want_trace, stream, workspace_limit)
+                query_offset, True, want_poles, want_trace, stream, workspace_limit, graph)
 
 
 def rrs_depth_projection(X, Z, K, n_refine, cap_shrink, seed=0, precision="f64", query_offset=0,
-                         want_poles=False, want_trace=False, stream=None, workspace_limit=0):
+                         want_poles=False, want_trace=False, stream=None, workspace_limit=0,
+                         graph=False):
     """Projection depth of each row of Z; returns dict(depth[, poles, trace])."""
     return _run("rrs_depth_projection", X, Z, K, n_refine, cap_shrink, seed, precision,
-                query_offset, False, want_poles, want_trace, stream, workspace_limit)
+                query_offset, False, want_poles, want_trace, stream, workspace_limit, graph)
 
 
 def rrs_depth_apd(X, Z, K, n_refine, cap_shrink, seed=0, precision="f64", query_offset=0,
-                  want_poles=False, want_trace=False, stream=None, workspace_limit=0):
+                  want_poles=False, want_trace=False, stream=None, workspace_limit=0,
+                  graph=False):
     """Asymmetric projection depth of each row of Z; returns dict(depth[, poles, trace])."""
     return _run("rrs_depth_apd", X, Z, K, n_refine, cap_shrink, seed, precision, query_offset,
-                False, want_poles, want_trace, stream, workspace_limit)
+                False, want_poles, want_trace, stream, workspace_limit, graph)
 
 
 DEPTH_FUNCS = {"halfspace": rrs_depth_halfspace, "projection": rrs_depth_projection,

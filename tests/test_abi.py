@@ -37,10 +37,11 @@ def test_version():
 
 
 def test_opts_layout_matches_header():
-    # int32, int32, void*, int64, double*, int64*, size_t on LP64
-    assert ctypes.sizeof(rrs.rrs_opts) == 48
+    # int32, int32, void*, int64, double*, int64*, size_t, uint32, uint32 on LP64
+    assert ctypes.sizeof(rrs.rrs_opts) == 56
     assert rrs.rrs_opts.stream.offset == 8
     assert rrs.rrs_opts.workspace_limit.offset == 40
+    assert rrs.rrs_opts.flags.offset == 48
 
 
 @pytest.mark.parametrize("kw,frag", [

@@ -335,3 +335,54 @@ def test_select_fast_path_dominates_on_centred_columns():
     ref = oracle.rrs_depth("projection", w.X, w.Z, w.K, w.n_refine, w.cap_shrink, 0)["depth"]
     assert np.array_equal(got, ref)
     assert fast > 0 and fb / (fast + fb) < 0.02, (fast, fb)
+
+
+@pytest.mark.parametrize("notion", ["halfspace", "projection"])
+@pytest.mark.parametrize("prec", MFMA_EXACT)
+def test_gemm_variants_and_autotuner_agree(notion, prec, monkeypatch):
+    """Every matrix-core GEMM variant (forced with RRS_TUNE=v+1) and the
+    autotuner's own choice give the same exact results."""
+    w = workloads.small(notion, 1700, 9, 10, 200, 4, 0.5, law="gaussian", seed_cfg=91)
+    ref = oracle.rrs_depth(notion, w.X, w.Z, w.K, w.n_refine, w.cap_shrink, 0)
+    pairs = w.projections
+    for mode in ("1", "2", ""):
+        monkeypatch.setenv("RRS_TUNE", mode)
+        rrs.rrs_profile_enable(True)
+        got = rrs.depth(notion, w.X, w.Z, w.K, w.n_refine, w.cap_shrink, 0, precision=prec)
+        rechecked = rrs.rrs_profile_counter("recheck_pairs")
+        fast = rrs.rrs_profile_counter("select_fast")
+        fallback = rrs.rrs_profile_counter("select_fallback")
+        rrs.rrs_profile_enable(False)
+        assert np.array_equal(got["depth"], ref["depth"]), mode
+        # a variant with wrong binary32 values would still be exact (everything
+        # rechecked or sent to the exact fallback) but slow: both stay rare
+        assert rechecked <= 0.02 * pairs, (mode, rechecked)
+        assert fallback <= 0.05 * max(fast + fallback, 1), (mode, fast, fallback)
+
+
+@pytest.mark.parametrize("notion,prec", [("halfspace", "bf16"), ("projection", "f32"),
+                                         ("apd", "f64"), ("halfspace", "f64")])
+def test_graph_replays_match_eager(notion, prec):
+    """RRS_FLAG_GRAPH: the first call captures the device work, later calls
+    replay it.  Every replay, with eager calls and host syncs between them,
+    must give the eager result."""
+    import torch
+    w = workloads.small(notion, 2500, 6, 24, 300, 5, 0.5, law="gaussian", seed_cfg=93)
+    dev = torch.device("cuda:0")
+    X = torch.from_numpy(w.X).to(dev)
+    Z = torch.from_numpy(w.Z).to(dev)
+    s = torch.cuda.Stream()
+    eager = rrs.depth(notion, X, Z, w.K, w.n_refine, w.cap_shrink, 4, precision=prec)
+    ref = eager["depth"].cpu().numpy()
+    for rep in range(4):
+        with torch.cuda.stream(s):
+            got = rrs.depth(notion, X, Z, w.K, w.n_refine, w.cap_shrink, 4, precision=prec,
+                            stream=s, graph=True)
+        torch.cuda.synchronize()
+        assert np.array_equal(got["depth"].cpu().numpy(), ref), rep
+        # eager work in between replays
+        other = rrs.depth(notion, X, Z[:5], w.K, w.n_refine, w.cap_shrink, 9, precision=prec)
+        torch.cuda.synchronize()
+        assert other["depth"].shape[0] == 5
+    oref = oracle.rrs_depth(notion, w.X, w.Z, w.K, w.n_refine, w.cap_shrink, 4)["depth"]
+    assert np.array_equal(ref, oref)
