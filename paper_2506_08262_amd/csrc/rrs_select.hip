@@ -517,60 +517,91 @@ __device__ void select_pair_stream(const double *__restrict__ col, int64_t n, do
         }
     }
     __syncthreads();
-    bool fast = sh.fast != 0;
-    if (fast) {
-        const uint32_t Lk = sh.Lk, R = sh.R, bsh = sh.sh, tau = sh.tau;
-        uint32_t below = 0;
+    bool fast = true;
+    {
+        // the sampled bracket, or the whole key range when too few samples
+        // took part
+        uint32_t Lk = sh.Lk, R = sh.R, bsh = sh.sh;
+        const uint32_t tau = sh.tau;
+        if (sh.fast == 0) {
+            Lk = 0u;
+            R = 0xFFFFFFFFu;
+            bsh = 24u;
+        }
         const uint32_t dummy = (uint32_t)kBins + (uint32_t)lane;
-        for (int64_t i0 = tid; i0 < n; i0 += (int64_t)kUnroll * kT) {
-            double t[kUnroll];
-#pragma unroll
-            for (int u = 0; u < kUnroll; ++u) {
-                const int64_t i = i0 + (int64_t)u * kT;
-                t[u] = i < n ? col[i] : 0.0;
-            }
-#pragma unroll
-            for (int u = 0; u < kUnroll; ++u) {
-                double x;
-                const bool part = i0 + (int64_t)u * kT < n && phase_val<PH>(t[u], med, x);
-                const uint32_t kx = part ? bin_key<PH>(x, tau) : 0xFFFFFFFFu;
-                const uint32_t dk = kx - Lk;
-                below += (part && kx < Lk) ? 1u : 0u;
-                atomicAdd(&sh.hist[(part && dk <= R) ? (dk >> bsh) : dummy], 1u);
-            }
-        }
-        for (int off = 32; off > 0; off >>= 1) below += (uint32_t)__shfl_xor((int)below, off);
-        if (lane == 0 && below) atomicAdd(&sh.below, below);
-        __syncthreads();
-        if (tid < 64) {
-            const uint64_t base = sh.below;
-            uint32_t bA, rA, cA, bB, rB, cB;
-            bool fA, fB;
-            scan_hist(sh.hist, base, k, bA, rA, cA, fA);
-            scan_hist(sh.hist, base, k + 1, bB, rB, cB, fB);
-            if (fA) {
-                sh.binA = bA;
-                sh.rankA = rA;
-                sh.cntA = cA;
-            }
-            if (fB) {
-                sh.binB = bB;
-                sh.rankB = rB;
-                sh.cntB = cB;
-            }
-            const uint64_t ma = __ballot(fA), mb = __ballot(fB);
-            if (lane == 0) sh.fast = (ma != 0 && (!pair || mb != 0)) ? 1 : 0;
-        }
-        __syncthreads();
-        fast = sh.fast != 0;
         uint32_t bA = 0, rA = 0, bB = 0, rB = 0;
-        if (fast) {
-            bA = sh.binA;
-            rA = sh.rankA;
-            bB = pair ? sh.binB : bA;
-            rB = pair ? sh.rankB : rA;
-            const bool same = bB == bA;
-            fast = sh.cntA <= (uint32_t)kCapA && (same || sh.cntB <= (uint32_t)kCapB);
+        // histogram passes: the first bins the bracket; while a target bin
+        // holds more values than can be collected (long columns), the next
+        // pass bins just the target bins 256 times finer
+        for (int level = 0;; ++level) {
+            uint32_t below = 0;
+            for (int64_t i0 = tid; i0 < n; i0 += (int64_t)kUnroll * kT) {
+                double t[kUnroll];
+#pragma unroll
+                for (int u = 0; u < kUnroll; ++u) {
+                    const int64_t i = i0 + (int64_t)u * kT;
+                    t[u] = i < n ? col[i] : 0.0;
+                }
+#pragma unroll
+                for (int u = 0; u < kUnroll; ++u) {
+                    double x;
+                    const bool part = i0 + (int64_t)u * kT < n && phase_val<PH>(t[u], med, x);
+                    const uint32_t kx = part ? bin_key<PH>(x, tau) : 0xFFFFFFFFu;
+                    const uint32_t dk = kx - Lk;
+                    below += (part && kx < Lk) ? 1u : 0u;
+                    atomicAdd(&sh.hist[(part && dk <= R) ? (dk >> bsh) : dummy], 1u);
+                }
+            }
+            for (int off = 32; off > 0; off >>= 1)
+                below += (uint32_t)__shfl_xor((int)below, off);
+            if (lane == 0 && below) atomicAdd(&sh.below, below);
+            __syncthreads();
+            if (tid < 64) {
+                const uint64_t base = sh.below;
+                uint32_t fbA, frA, fcA, fbB, frB, fcB;
+                bool fA, fB;
+                scan_hist(sh.hist, base, k, fbA, frA, fcA, fA);
+                scan_hist(sh.hist, base, k + 1, fbB, frB, fcB, fB);
+                if (fA) {
+                    sh.binA = fbA;
+                    sh.rankA = frA;
+                    sh.cntA = fcA;
+                }
+                if (fB) {
+                    sh.binB = fbB;
+                    sh.rankB = frB;
+                    sh.cntB = fcB;
+                }
+                const uint64_t ma = __ballot(fA), mb = __ballot(fB);
+                if (lane == 0) sh.fast = (ma != 0 && (!pair || mb != 0)) ? 1 : 0;
+            }
+            __syncthreads();
+            fast = sh.fast != 0;
+            if (!fast) {
+                // the sampled bracket missed the rank: bin the whole key range
+                // instead (then narrow as usual)
+                if (level > 0 || (Lk == 0u && R == 0xFFFFFFFFu)) break;
+                Lk = 0u;
+                R = 0xFFFFFFFFu;
+                bsh = 24u;
+            } else {
+                bA = sh.binA;
+                rA = sh.rankA;
+                bB = pair ? sh.binB : bA;
+                rB = pair ? sh.rankB : rA;
+                const bool same = bB == bA;
+                fast = sh.cntA <= (uint32_t)kCapA && (same || sh.cntB <= (uint32_t)kCapB);
+                if (fast || bsh == 0 || level == 6) break;
+                // narrow to the target bins and start over
+                Lk = Lk + (bA << bsh);
+                R = ((bB - bA + 1) << bsh) - 1;
+                const uint32_t nb = 32u - (uint32_t)__clz((int)(R | 1u));
+                bsh = nb > 8u ? nb - 8u : 0u;
+            }
+            __syncthreads();
+            sh.hist[tid] = 0;
+            if (tid == 0) sh.below = 0;
+            __syncthreads();
         }
         if (fast) {
             for (int64_t i0 = tid; i0 < n; i0 += (int64_t)kUnroll * kT) {

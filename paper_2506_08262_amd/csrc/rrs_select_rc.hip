@@ -44,7 +44,8 @@ using namespace sel;
 
 constexpr int kT = 256;
 constexpr int kBins = 256;
-constexpr int kCapW = 512;       // candidates of one window
+constexpr int kCapW = 2048;      // candidates of one window
+constexpr int kQuad = 512;       // up to this many, rank candidates by all-pairs counts
 constexpr int kRadixCand = 64;
 constexpr int kUnroll = 4;
 constexpr int kDs = 128;         // coordinates kept in LDS for the recomputation
@@ -242,6 +243,60 @@ struct RegSrc {
     }
 };
 
+// Rank r (and r + 1 when pair) among the n candidate values held in LDS:
+// radix select over their order-preserving 64-bit keys, 8 bits per pass.
+__device__ void lds_rank_pair(RcShared &sh, uint32_t nc, uint64_t r, bool pair, double &a,
+                              double &b)
+{
+    const int tid = threadIdx.x;
+    uint64_t prefix = 0, pmask = 0, k = r;
+    for (int shift = 56; shift >= 0; shift -= 8) {
+        sh.hist[tid] = 0;
+        __syncthreads();
+        for (uint32_t p = tid; p < nc; p += kT) {
+            const uint64_t key = order_key(sh.cval[p]);
+            if ((key & pmask) == prefix) atomicAdd(&sh.hist[(uint32_t)(key >> shift) & 255u], 1u);
+        }
+        __syncthreads();
+        if (tid < 64) {
+            uint32_t bin, rin, cnt;
+            bool found;
+            scan_hist(sh.hist, 0, k, bin, rin, cnt, found);
+            if (found) {
+                sh.sel_bucket = bin;
+                sh.sel_before = (uint32_t)(k - rin);
+            }
+        }
+        __syncthreads();
+        k -= sh.sel_before;
+        prefix |= (uint64_t)sh.sel_bucket << shift;
+        pmask |= 0xFFull << shift;
+        __syncthreads();
+    }
+    a = key_value(prefix);
+    b = a;
+    if (!pair) return;
+    // the next value: A again if more than r + 1 keys are <= A, else the
+    // smallest key above A
+    if (tid == 0) {
+        sh.count = 0;
+        sh.minkey = ~0ull;
+    }
+    __syncthreads();
+    uint32_t le = 0;
+    uint64_t mn = ~0ull;
+    for (uint32_t p = tid; p < nc; p += kT) {
+        const uint64_t key = order_key(sh.cval[p]);
+        le += key <= prefix;
+        if (key > prefix && key < mn) mn = key;
+    }
+    if (le) atomicAdd(&sh.count, le);
+    if (mn != ~0ull) atomicMin((unsigned long long *)&sh.minkey, (unsigned long long)mn);
+    __syncthreads();
+    b = ((uint64_t)sh.count >= r + 2) ? a : key_value(sh.minkey);
+    __syncthreads();
+}
+
 // Exact radix select (rank k) over the recomputed values of phase PH.
 template <int PH, bool EXACT>
 __device__ uint64_t rc_radix_kth(const Col &C, double med, uint64_t k, RcShared &sh)
@@ -405,33 +460,70 @@ __device__ bool rc_select(const Col &C, const SRC &src, double med, double sig, 
         }
     }
     __syncthreads();
-    bool fast = sh.fast != 0;
-    if (fast) {
-        const uint32_t Lk = sh.Lk, R = sh.R, bsh = sh.sh, tau = sh.tau;
+    bool fast = true;
+    {
+        // the sampled bracket, or the whole key range when too few samples
+        // took part
+        uint32_t Lk = sh.Lk, R = sh.R, bsh = sh.sh;
+        const uint32_t tau = sh.tau;
+        if (sh.fast == 0) {
+            Lk = 0u;
+            R = 0xFFFFFFFFu;
+            bsh = 24u;
+        }
         uint32_t nbelow = 0;
         const uint32_t dummy = (uint32_t)kBins + (uint32_t)lane;
-        src.each([&](int64_t, float sv, bool live) {
-            const uint32_t kx = fbin_key<PH>(approx_v<PH>(sv, sigf), tau);
-            const uint32_t dk = kx - Lk;
-            nbelow += (live && kx < Lk) ? 1u : 0u;
-            atomicAdd(&sh.hist[(live && dk <= R) ? (dk >> bsh) : dummy], 1u);
-        });
-        for (int off = 32; off > 0; off >>= 1) nbelow += (uint32_t)__shfl_xor((int)nbelow, off);
-        if (lane == 0 && nbelow) atomicAdd(&sh.below, nbelow);
-        __syncthreads();
-        if (tid < 64) {
-            const uint64_t base = sh.below;
-            uint32_t bA, rA, cA, bB, rB, cB;
-            bool fA, fB;
-            scan_hist(sh.hist, base, k, bA, rA, cA, fA);
-            scan_hist(sh.hist, base, k + 1, bB, rB, cB, fB);
-            if (fA) sh.binA = bA;
-            if (fB) sh.binB = bB;
-            const uint64_t ma = __ballot(fA), mb = __ballot(fB);
-            if (lane == 0) sh.fast = (ma != 0 && (!pair || mb != 0)) ? 1 : 0;
+        // histogram passes: the first bins the bracket; while the target bins
+        // hold more than half the candidate room (long columns), the next pass
+        // bins just those bins 256 times finer
+        for (int level = 0;; ++level) {
+            nbelow = 0;
+            src.each([&](int64_t, float sv, bool live) {
+                const uint32_t kx = fbin_key<PH>(approx_v<PH>(sv, sigf), tau);
+                const uint32_t dk = kx - Lk;
+                nbelow += (live && kx < Lk) ? 1u : 0u;
+                atomicAdd(&sh.hist[(live && dk <= R) ? (dk >> bsh) : dummy], 1u);
+            });
+            for (int off = 32; off > 0; off >>= 1)
+                nbelow += (uint32_t)__shfl_xor((int)nbelow, off);
+            if (lane == 0 && nbelow) atomicAdd(&sh.below, nbelow);
+            __syncthreads();
+            if (tid < 64) {
+                const uint64_t base = sh.below;
+                uint32_t bA, rA, cA, bB, rB, cB;
+                bool fA, fB;
+                scan_hist(sh.hist, base, k, bA, rA, cA, fA);
+                scan_hist(sh.hist, base, k + 1, bB, rB, cB, fB);
+                if (fA) sh.binA = bA;
+                if (fB) sh.binB = bB;
+                const uint64_t ma = __ballot(fA), mb = __ballot(fB);
+                if (lane == 0) sh.fast = (ma != 0 && (!pair || mb != 0)) ? 1 : 0;
+            }
+            __syncthreads();
+            fast = sh.fast != 0;
+            if (!fast) {
+                // the sampled bracket missed the rank: bin the whole key range
+                // instead (then narrow as usual)
+                if (level > 0 || (Lk == 0u && R == 0xFFFFFFFFu)) break;
+                Lk = 0u;
+                R = 0xFFFFFFFFu;
+                bsh = 24u;
+            } else {
+                const uint32_t bA = sh.binA, bB = pair ? sh.binB : sh.binA;
+                uint32_t held = 0;
+                for (uint32_t b = bA; b <= bB; ++b) held += sh.hist[b];
+                if (held <= (uint32_t)kCapW / 2 || bsh == 0 || level == 6) break;
+                // narrow to the target bins and start over
+                Lk = Lk + (bA << bsh);
+                R = ((bB - bA + 1) << bsh) - 1;
+                const uint32_t nb = 32u - (uint32_t)__clz((int)(R | 1u));
+                bsh = nb > 8u ? nb - 8u : 0u;
+            }
+            __syncthreads();
+            sh.hist[tid] = 0;
+            if (tid == 0) sh.below = 0;
+            __syncthreads();
         }
-        __syncthreads();
-        fast = sh.fast != 0;
         if (fast) {
             const uint32_t bA = sh.binA, bB = pair ? sh.binB : sh.binA;
             // approximations of the target bins lie in [vlo, vhi]
@@ -469,20 +561,24 @@ __device__ bool rc_select(const Col &C, const SRC &src, double med, double sig, 
                     sh.cval[p] = exact_v<PH>(exact_t<EXACT>(C, (int64_t)sh.cidx[p]), med);
                 __syncthreads();
                 const uint64_t rA = k - B, rB = k + 1 - B;
-                for (uint32_t p = tid; p < nc; p += kT) {
-                    const double mine = sh.cval[p];
-                    uint32_t lt = 0, le = 0;
-                    for (uint32_t x = 0; x < nc; ++x) {
-                        const double o = sh.cval[x];
-                        lt += (o < mine);
-                        le += (o <= mine);
+                if (nc <= (uint32_t)kQuad) {
+                    for (uint32_t p = tid; p < nc; p += kT) {
+                        const double mine = sh.cval[p];
+                        uint32_t lt = 0, le = 0;
+                        for (uint32_t x = 0; x < nc; ++x) {
+                            const double o = sh.cval[x];
+                            lt += (o < mine);
+                            le += (o <= mine);
+                        }
+                        if (lt <= rA && rA < le) sh.resA = mine;
+                        if (pair && lt <= rB && rB < le) sh.resB = mine;
                     }
-                    if (lt <= rA && rA < le) sh.resA = mine;
-                    if (pair && lt <= rB && rB < le) sh.resB = mine;
+                    __syncthreads();
+                    a = sh.resA;
+                    b = pair ? sh.resB : a;
+                } else {
+                    lds_rank_pair(sh, nc, rA, pair, a, b);
                 }
-                __syncthreads();
-                a = sh.resA;
-                b = pair ? sh.resB : a;
                 *below = B;
                 if (stats && tid == 0) atomicAdd(&stats[0], 1u);
                 return true;

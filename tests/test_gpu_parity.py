@@ -386,3 +386,18 @@ def test_graph_replays_match_eager(notion, prec):
         assert other["depth"].shape[0] == 5
     oref = oracle.rrs_depth(notion, w.X, w.Z, w.K, w.n_refine, w.cap_shrink, 4)["depth"]
     assert np.array_equal(ref, oref)
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("notion", ["projection", "apd"])
+def test_select_recovers_when_samples_mislead(prec, notion):
+    """The long-column selects sample 64 evenly spaced entries to bracket the
+    rank; outliers planted exactly there make the bracket miss, and the
+    select must recover (whole key range, then narrowing) with exact results."""
+    n = 20001
+    w = workloads.small(notion, n, 4, 4, 40, 2, 0.5, law="gaussian", seed_cfg=97)
+    X = w.X.copy()
+    pos = [((2 * t + 1) * n) // 128 for t in range(64)]
+    X[pos] = 1e3 * np.sign(np.random.default_rng(5).standard_normal((64, 4)))
+    w.X = X
+    _compare(notion, w, precision=prec)
