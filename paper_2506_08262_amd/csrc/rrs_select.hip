@@ -179,6 +179,11 @@ __device__ uint64_t radix_next_g(const double *__restrict__ col, int64_t n, doub
     return res;
 }
 
+template <int PH>
+__device__ void select_pair_stream(const double *__restrict__ col, int64_t n, double med,
+                                   uint64_t cnt, uint64_t k, bool pair, double &a, double &b,
+                                   RegShared &sh, uint32_t *stats);
+
 // ---------------------------------------------------------------------------
 // The k-th (and, if pair, the (k+1)-th) smallest of the cnt values taking
 // part in phase PH; vals holds the column in phase PH.
@@ -361,14 +366,12 @@ __device__ __forceinline__ void select_pair(double (&vals)[VPT],
             return;
         }
     }
-    // exact fallback over global memory; the barrier keeps every wave out of
-    // the shared histogram until all have finished reading it
+    // a miss: the streamed select over the same column in global memory
+    // (rebracketing and narrowing; its own last resort is the exact radix
+    // select); the barrier keeps every wave out of the shared histogram until
+    // all have finished reading it
     __syncthreads();
-    if (stats && tid == 0) atomicAdd(&stats[1], 1u);
-    const uint64_t A = radix_kth_g<PH>(col, n, med, k, sh);
-    a = key_value(A);
-    b = a;
-    if (pair) b = key_value(radix_next_g<PH>(col, n, med, k, A, sh));
+    select_pair_stream<PH>(col, n, med, cnt, k, pair, a, b, sh, stats);
 }
 
 template <int PH, int VPT>

@@ -186,6 +186,7 @@ __device__ __forceinline__ double key_hi_value(uint32_t K, uint32_t tau)
 // Where a select reads the column's binary32 projections from.
 // StreamSrc: global memory, 4 loads in flight per lane (any n).
 struct StreamSrc {
+    static constexpr int kMaxLevel = 6;  // rebracket / narrowing passes allowed
     const float *s;
     int64_t n;
     __device__ __forceinline__ float sample(int slot) const
@@ -217,6 +218,7 @@ struct StreamSrc {
 // array in registers.
 template <int VPT>
 struct RegSrc {
+    static constexpr int kMaxLevel = 0;  // short columns: one pass, misses fall back
     float (&v)[VPT];
     int64_t n;
     __device__ __forceinline__ float sample(int slot) const
@@ -460,13 +462,15 @@ __device__ bool rc_select(const Col &C, const SRC &src, double med, double sig, 
         }
     }
     __syncthreads();
-    bool fast = true;
-    {
+    // register-resident columns keep a single pass (a miss falls back);
+    // streamed columns rebracket and narrow instead
+    bool fast = SRC::kMaxLevel > 0 || sh.fast != 0;
+    if (fast) {
         // the sampled bracket, or the whole key range when too few samples
         // took part
         uint32_t Lk = sh.Lk, R = sh.R, bsh = sh.sh;
         const uint32_t tau = sh.tau;
-        if (sh.fast == 0) {
+        if (SRC::kMaxLevel > 0 && sh.fast == 0) {
             Lk = 0u;
             R = 0xFFFFFFFFu;
             bsh = 24u;
@@ -501,6 +505,7 @@ __device__ bool rc_select(const Col &C, const SRC &src, double med, double sig, 
             }
             __syncthreads();
             fast = sh.fast != 0;
+            if (level >= SRC::kMaxLevel) break;
             if (!fast) {
                 // the sampled bracket missed the rank: bin the whole key range
                 // instead (then narrow as usual)
@@ -512,7 +517,7 @@ __device__ bool rc_select(const Col &C, const SRC &src, double med, double sig, 
                 const uint32_t bA = sh.binA, bB = pair ? sh.binB : sh.binA;
                 uint32_t held = 0;
                 for (uint32_t b = bA; b <= bB; ++b) held += sh.hist[b];
-                if (held <= (uint32_t)kCapW / 2 || bsh == 0 || level == 6) break;
+                if (held <= (uint32_t)kCapW / 2 || bsh == 0) break;
                 // narrow to the target bins and start over
                 Lk = Lk + (bA << bsh);
                 R = ((bB - bA + 1) << bsh) - 1;
@@ -586,6 +591,12 @@ __device__ bool rc_select(const Col &C, const SRC &src, double med, double sig, 
         }
     }
     __syncthreads();
+    if (SRC::kMaxLevel == 0) {
+        // a register-resident column that missed: the streamed select over
+        // the same column in global memory (rebracketing, narrowing)
+        return rc_select<PH, EXACT>(C, StreamSrc{C.s, C.n}, med, sig, E, k, pair, a, b, below,
+                                    sh, stats);
+    }
     if (stats && tid == 0) atomicAdd(&stats[1], 1u);
     const uint64_t A = rc_radix_kth<PH, EXACT>(C, med, k, sh);
     a = key_value(A);
