@@ -30,19 +30,24 @@ HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
 FP64_VALU_PEAK_TFLOPS = 78.6   # 256 CU x 4 SIMD x 16 lanes x 2 flop x 2.4 GHz
 MFMA_PEAK_TFLOPS = {"bf16": 2500.0, "f32": 157.3, "f32_plain": 157.3}   # dense matrix cores
 
+# workload -> (generator, notion, default precision: the fastest exact form)
 WORKLOADS = {
-    "c2": ("c2", "projection"),
-    "c1": ("c1", "halfspace"),
-    "c1b": ("c1b", "halfspace"),
-    "c3": ("c3", "apd"),
-    "c5h": ("c5", "halfspace"),
-    "c5p": ("c5", "projection"),
+    "c2": ("c2", "projection", "f32"),
+    "c1": ("c1", "halfspace", "f64"),
+    "c1b": ("c1b", "halfspace", "f64"),
+    "c3": ("c3", "apd", "bf16"),
+    "c5h": ("c5", "halfspace", "bf16"),
+    "c5p": ("c5", "projection", "f32"),
 }
 
 
 def kernel_model(name: str, notion: str, d: int, precision: str = "f64"):
     """Algorithmic cost per work unit of each kernel (bytes or flops the method needs)."""
-    if name == "k_gemm_sign":
+    if name == "k_gemm" and notion != "halfspace":
+        # projection / APD: the GEMM writes each binary32 projection once
+        return {"bound": "hbm", "per_unit": 4.0, "unit": "GB/s", "peak": HBM_PEAK_GBS,
+                "scale": 1e-9, "what": "4 B written per projection (binary32 column)"}
+    if name == "k_gemm":
         # one projection is a d-term dot product: 2d flops, whatever the
         # padding of K and the number of split products the kernel issues
         kp = (d + 2 + 15) // 16 * 16 if precision == "bf16" else (d + 1 + 7) // 8 * 8
@@ -59,6 +64,9 @@ def kernel_model(name: str, notion: str, d: int, precision: str = "f64"):
                     "what": f"2d = {2 * d} FP64 flops per projection"}
         return {"bound": "hbm", "per_unit": 8.0, "unit": "GB/s", "peak": HBM_PEAK_GBS,
                 "scale": 1e-9, "what": "8 B written per projection (binary64 column)"}
+    if name == "k_select" and precision != "f64":
+        return {"bound": "hbm", "per_unit": 4.0, "unit": "GB/s", "peak": HBM_PEAK_GBS,
+                "scale": 1e-9, "what": "4 B read per projection (binary32 column)"}
     if name == "k_select":
         return {"bound": "hbm", "per_unit": 8.0, "unit": "GB/s", "peak": HBM_PEAK_GBS,
                 "scale": 1e-9, "what": "8 B read per projection (binary64 column)"}
@@ -115,7 +123,7 @@ def serve_main(args):
     offered = sum(r.projections for r in stream) / stream[-1].arrival
     print(f"[bench] serving stream: {len(stream)} requests over {stream[-1].arrival:.3f} s, "
           f"offered {offered:.3g} projections/s", file=sys.stderr, flush=True)
-    prec = {"halfspace": args.serve_h_precision, "projection": "f64"}
+    prec = {"halfspace": args.serve_h_precision, "projection": args.serve_p_precision}
     with rrs.Context(device=0, slots=args.slots, hbm_budget=args.hbm_budget << 30) as ctx:
         dss = [ctx.put(r.X) for r in stream]
         print("[bench] data sets resident", file=sys.stderr, flush=True)
@@ -155,7 +163,7 @@ def serve_main(args):
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": f"halfspace {prec['halfspace']}, projection f64",
+        "dtype": f"halfspace {prec['halfspace']}, projection {prec['projection']}",
         "data": "synthetic",
         "config": {"workload": f"c4: serving stream of {len(stream)} requests, Poisson 200/s, "
                                "halfspace/projection 1/2 each, own data set per request "
@@ -188,8 +196,9 @@ def main():
     ap.add_argument("--slots", type=int, default=4, help="c4: concurrent requests")
     ap.add_argument("--hbm-budget", type=int, default=64, help="c4: serving budget in GiB")
     ap.add_argument("--serve-h-precision", default="bf16", help="c4: halfspace precision")
-    ap.add_argument("--precision", default="f64", choices=["f64", "f32", "bf16", "f32_plain"],
-                    help="projection arithmetic (matrix-core forms: halfspace depth only)")
+    ap.add_argument("--serve-p-precision", default="f32", help="c4: projection precision")
+    ap.add_argument("--precision", default=None, choices=["f64", "f32", "bf16", "f32_plain"],
+                    help="projection arithmetic (default: the workload's fastest exact form)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-queries", type=int, default=32)
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -208,7 +217,9 @@ def main():
     import torch
 
     from paper_2506_08262_amd import rrs, workloads
-    wname, notion = WORKLOADS[args.workload]
+    wname, notion, default_prec = WORKLOADS[args.workload]
+    if args.precision is None:
+        args.precision = default_prec
     w = workloads.make(wname, **({"notion": notion} if wname == "c5" else {}))
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")

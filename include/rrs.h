@@ -157,7 +157,7 @@ int32_t rrs_version(void);
  * copies up to max_entries totals (one per kernel that ran) into out and
  * returns how many it wrote (out may be NULL to count them).  work_units is
  * the sum over launches of the units each launch processed: projections
- * (query x direction x point) for k_proj_f64, k_select and k_gemm_sign,
+ * (query x direction x point) for k_proj_f64, k_select and k_gemm,
  * coordinates for k_gen_dirs, directions for k_argmin_pole (0 for k_recheck,
  * which handles the pairs the matrix-core forms left uncertain). */
 typedef struct {

@@ -39,7 +39,7 @@ size_t carve_size(const size_t *sizes, int k)
 }
 
 const char *const kKernelNames[K_COUNT] = {"k_gen_dirs",    "k_proj_f64",  "k_select",
-                                           "k_argmin_pole", "k_gemm_sign", "k_recheck",
+                                           "k_argmin_pole", "k_gemm",      "k_recheck",
                                            "k_misc"};
 
 hipEvent_t Profiler::get()

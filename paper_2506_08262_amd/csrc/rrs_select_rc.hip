@@ -129,19 +129,22 @@ __device__ __forceinline__ bool fkey_finite(uint32_t k)
     return PH == 0 ? k < 0xFF800000u : k < 0x7F800000u;
 }
 
-// Bracket key on binary32 bits with magnitudes below tau collapsed onto the
-// key of zero (as bin_key does on binary64 high words); monotone in x.
+// Bracket key on binary32 bits with magnitudes below tau (>= 1) collapsed
+// onto the key of zero (as bin_key does on binary64 high words); monotone in
+// x.  With e = max(mag - (tau - 1), 0) (0 for collapsed magnitudes, else
+// 1 + mag - tau): phase 0 keys are 2^31 + e for x >= 0 and 2^31 - e for
+// x < 0; phase 1 keys (x >= 0) are e.  taum1 = tau - 1.
 template <int PH>
-__device__ __forceinline__ uint32_t fbin_key(float x, uint32_t tau)
+__device__ __forceinline__ uint32_t fbin_key(float x, uint32_t taum1)
 {
     const uint32_t b = __float_as_uint(x);
-    const uint32_t mag = b & 0x7FFFFFFFu;
-    const uint32_t dd = mag - tau;
     if (PH == 0) {
-        if (mag < tau) return 0x80000000u;
-        return (b >> 31) ? 0x7FFFFFFFu - dd : 0x80000001u + dd;
+        const uint32_t mag = b & 0x7FFFFFFFu;
+        const uint32_t e = (mag > taum1 ? mag : taum1) - taum1;
+        const uint32_t sgn = (uint32_t)((int32_t)b >> 31);  // 0 or all ones
+        return 0x80000000u + ((e ^ sgn) - sgn);
     }
-    return mag < tau ? 0u : 1u + dd;
+    return (b > taum1 ? b : taum1) - taum1;
 }
 
 __device__ __forceinline__ float lane_bcast_f(float x, int src)
@@ -237,10 +240,12 @@ struct RegSrc {
         // conversions, keys) are recomputed instead of being kept live
 #pragma unroll
         for (int u = 0; u < VPT; ++u) asm volatile("" : "+v"(v[u]));
+        // slots below n / kT are full for every lane (a scalar test)
+        const int nfull = (int)(n / kT);
 #pragma unroll
         for (int u = 0; u < VPT; ++u) {
             const int64_t i = (int64_t)threadIdx.x + (int64_t)kT * u;
-            f(i, v[u], i < n);
+            f(i, v[u], u < nfull || i < n);
         }
     }
 };
@@ -448,8 +453,9 @@ __device__ bool rc_select(const Col &C, const SRC &src, double med, double sig, 
             const float L = lane_bcast_f(xv, __ffsll((long long)mlo) - 1);
             const float H = lane_bcast_f(xv, __ffsll((long long)mhi) - 1);
             tau = __float_as_uint(fmaxf(fabsf(L), fabsf(H)) * 0x1p-6f) & 0x7FFFFFFFu;
-            Lk = fbin_key<PH>(L, tau);
-            Hk = fbin_key<PH>(H, tau);
+            if (tau < 1u) tau = 1u;
+            Lk = fbin_key<PH>(L, tau - 1u);
+            Hk = fbin_key<PH>(H, tau - 1u);
         }
         if (lane == 0) {
             const uint32_t R = Hk - Lk;
@@ -482,11 +488,14 @@ __device__ bool rc_select(const Col &C, const SRC &src, double med, double sig, 
         // bins just those bins 256 times finer
         for (int level = 0;; ++level) {
             nbelow = 0;
+            // bins 0..255 cover keys Lk .. Lk + (256 << bsh) - 1 (at least the
+            // bracket); keys outside go to the lane's dummy slot
             src.each([&](int64_t, float sv, bool live) {
-                const uint32_t kx = fbin_key<PH>(approx_v<PH>(sv, sigf), tau);
+                const uint32_t kx = fbin_key<PH>(approx_v<PH>(sv, sigf), tau - 1u);
                 const uint32_t dk = kx - Lk;
                 nbelow += (live && kx < Lk) ? 1u : 0u;
-                atomicAdd(&sh.hist[(live && dk <= R) ? (dk >> bsh) : dummy], 1u);
+                const uint32_t bin = dk >> bsh;
+                atomicAdd(&sh.hist[live ? (bin < dummy ? bin : dummy) : dummy], 1u);
             });
             for (int off = 32; off > 0; off >>= 1)
                 nbelow += (uint32_t)__shfl_xor((int)nbelow, off);
@@ -534,7 +543,7 @@ __device__ bool rc_select(const Col &C, const SRC &src, double med, double sig, 
             // approximations of the target bins lie in [vlo, vhi]
             const uint64_t klo = (uint64_t)Lk + ((uint64_t)bA << bsh);
             uint64_t khi = (uint64_t)Lk + (((uint64_t)bB + 1) << bsh) - 1;
-            if (khi > (uint64_t)Lk + R) khi = (uint64_t)Lk + R;
+            if (khi > 0xFFFFFFFFull) khi = 0xFFFFFFFFull;
             const double vlo = key_lo_value<PH>((uint32_t)klo, tau);
             const double vhi = key_hi_value<PH>((uint32_t)khi, tau);
             // phase 1 adds the roundings of sig to binary32 and of s - sig
