@@ -24,6 +24,7 @@
 #include <map>
 #include <mutex>
 #include <tuple>
+#include <type_traits>
 
 #include "rrs_launch.hpp"
 
@@ -220,14 +221,38 @@ struct GemmLds {
     };
     uint32_t red[4][kTN][2];
     float an[kTM];   // norm bounds of the tile's points (sign epilogue)
-    uint32_t unc[4][4][64];  // per wave, column tile and lane: uncertain elements
+};
+
+// Variant 2 (pipelined): both operands staged through LDS in K chunks of
+// kKC2, double-buffered; the global loads of chunk c + 1 are in flight while
+// the MFMAs of chunk c run.
+constexpr int kKC2 = 32;
+constexpr int kRow2h = kKC2 + 8;   // bf16 elements per staged row (80 B: 8-lane groups hit
+                                   // distinct 16-byte bank groups)
+constexpr int kRow2f = kKC2 + 4;   // binary32 elements per staged row (144 B)
+
+struct GemmLds2 {
+    union {
+        struct {
+            __bf16 a[2][2][kTM * kRow2h];  // [buffer][term]
+            __bf16 b[2][2][kTN * kRow2h];
+        } h;
+        struct {
+            float a[2][kTM * kRow2f];
+            float b[2][kTN * kRow2f];
+        } f;
+    };
+    uint32_t red[4][kTN][2];
+    float an[kTM];
 };
 
 enum { EPI_SIGN = 0, EPI_STORE = 1 };
 
 // the chunk-prefetch variant stages a B chunk with at most 8 pieces per thread
-static_assert(kTN * (kKC / 8) * 2 <= 256 * 8, "bf16 B chunk exceeds the staging registers");
-static_assert(kTN * (kKC / 4) <= 256 * 8, "binary32 B chunk exceeds the staging registers");
+static_assert(kTN * (kKC / 8) * 2 == 256 * 8 && kKC / 8 == 8,
+              "bf16 B chunk: 8 pieces per thread, index math by shifts");
+static_assert(kTN * (kKC / 4) == 256 * 8 && kKC / 4 == 16,
+              "binary32 B chunk: 8 pieces per thread, index math by shifts");
 
 // Variant 1 (chunk prefetch): per K chunk the B rows go global -> registers
 // -> LDS and every A fragment of the chunk is requested before the first
@@ -261,19 +286,16 @@ __device__ __forceinline__ void gemm_block_chunk(const void *__restrict__ A0,
         const int ns = kc / kStep;
         if (PREC == MFMA_BF16) {
             // B chunk: 128 rows x kc, two terms, 16-byte pieces (<= 8 per thread)
-            const int per_row = kc / 8;
-            const int total = kTN * per_row * 2;
+            const int vpr = kc / 8;
             bf16x8 bst[8];
 #pragma unroll
             for (int u = 0; u < 8; ++u) {
                 const int p = tid + 256 * u;
-                if (p < total) {
-                    const int term = p / (kTN * per_row);
-                    const int q = p - term * kTN * per_row;
-                    const int row = q / per_row, piece = q - row * per_row;
+                const int term = p >> 10, q = p & 1023;
+                const int row = q >> 3, piece = q & 7;
+                if (piece < vpr)
                     bst[u] = *(const bf16x8 *)((const __bf16 *)(term ? B1 : B0) +
                                                (J0 + row) * kp + k0 + piece * 8);
-                }
             }
             bf16x8 ah[kSteps][2], al[kSteps][2];
 #pragma unroll
@@ -288,12 +310,10 @@ __device__ __forceinline__ void gemm_block_chunk(const void *__restrict__ A0,
 #pragma unroll
             for (int u = 0; u < 8; ++u) {
                 const int p = tid + 256 * u;
-                if (p < total) {
-                    const int term = p / (kTN * per_row);
-                    const int q = p - term * kTN * per_row;
-                    const int row = q / per_row, piece = q - row * per_row;
+                const int term = p >> 10, q = p & 1023;
+                const int row = q >> 3, piece = q & 7;
+                if (piece < vpr)
                     *(bf16x8 *)(L.bh + (term * kTN + row) * kLdsRow16 + piece * 8) = bst[u];
-                }
             }
             __syncthreads();
 #pragma unroll
@@ -318,17 +338,15 @@ __device__ __forceinline__ void gemm_block_chunk(const void *__restrict__ A0,
                 }
             }
         } else {
-            const int per_row = kc / 4;
-            const int total = kTN * per_row;
+            const int vpr = kc / 4;
             f32x4 bst[8];
 #pragma unroll
             for (int u = 0; u < 8; ++u) {
                 const int p = tid + 256 * u;
-                if (p < total) {
-                    const int row = p / per_row, piece = p - row * per_row;
+                const int row = p >> 4, piece = p & 15;
+                if (piece < vpr)
                     bst[u] = *(const f32x4 *)((const float *)B0 + (J0 + row) * kp + k0 +
                                               piece * 4);
-                }
             }
             f32x4 a[kSteps][2];
 #pragma unroll
@@ -341,10 +359,8 @@ __device__ __forceinline__ void gemm_block_chunk(const void *__restrict__ A0,
 #pragma unroll
             for (int u = 0; u < 8; ++u) {
                 const int p = tid + 256 * u;
-                if (p < total) {
-                    const int row = p / per_row, piece = p - row * per_row;
-                    *(f32x4 *)(L.bf + row * kLdsRow32 + piece * 4) = bst[u];
-                }
+                const int row = p >> 4, piece = p & 15;
+                if (piece < vpr) *(f32x4 *)(L.bf + row * kLdsRow32 + piece * 4) = bst[u];
             }
             __syncthreads();
 #pragma unroll
@@ -399,22 +415,31 @@ __device__ __forceinline__ void gemm_block_steps(const void *__restrict__ A0,
         const int kc = (int)((kp - k0) < kKC ? (kp - k0) : kKC);
         // stage B[J0 .. J0 + 127][k0 .. k0 + kc) in LDS, 16 bytes per copy
         if (PREC == MFMA_BF16) {
-            const int per_row = kc / 8;  // 16-byte pieces per row and term
-            for (int p = tid; p < kTN * per_row * 2; p += 256) {
-                const int term = p / (kTN * per_row);
-                const int q = p - term * kTN * per_row;
-                const int row = q / per_row, piece = q - row * per_row;
-                const __bf16 *src = (const __bf16 *)(term ? B1 : B0) + (J0 + row) * kp + k0 +
-                                    piece * 8;
-                *(bf16x8 *)(L.bh + (term * kTN + row) * kLdsRow16 + piece * 8) =
-                    *(const bf16x8 *)src;
+            // 8 pieces of 16 bytes per row and term in a full chunk
+            const int vpr = kc / 8;
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int p = tid + 256 * u;
+                const int term = p >> 10, q = p & 1023;
+                const int row = q >> 3, piece = q & 7;
+                if (piece < vpr) {
+                    const __bf16 *src = (const __bf16 *)(term ? B1 : B0) + (J0 + row) * kp +
+                                        k0 + piece * 8;
+                    *(bf16x8 *)(L.bh + (term * kTN + row) * kLdsRow16 + piece * 8) =
+                        *(const bf16x8 *)src;
+                }
             }
         } else {
-            const int per_row = kc / 4;
-            for (int p = tid; p < kTN * per_row; p += 256) {
-                const int row = p / per_row, piece = p - row * per_row;
-                const float *src = (const float *)B0 + (J0 + row) * kp + k0 + piece * 4;
-                *(f32x4 *)(L.bf + row * kLdsRow32 + piece * 4) = *(const f32x4 *)src;
+            // 16 pieces of 16 bytes per row in a full chunk
+            const int vpr = kc / 4;
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int p = tid + 256 * u;
+                const int row = p >> 4, piece = p & 15;
+                if (piece < vpr) {
+                    const float *src = (const float *)B0 + (J0 + row) * kp + k0 + piece * 4;
+                    *(f32x4 *)(L.bf + row * kLdsRow32 + piece * 4) = *(const f32x4 *)src;
+                }
             }
         }
         __syncthreads();
@@ -471,6 +496,160 @@ __device__ __forceinline__ void gemm_block_steps(const void *__restrict__ A0,
     }
 }
 
+// Variant 2: see GemmLds2.  Each thread moves 8 A pieces and 4 B pieces of
+// 16 bytes per chunk (256 rows x 64 B x 2 terms, 128 rows x 64 B x 2 terms for
+// bf16; 256 x 128 B and 128 x 128 B for binary32).
+template <int PREC>
+__device__ __forceinline__ void gemm_block_pipe(const void *__restrict__ A0,
+                                                const void *__restrict__ A1, int64_t n,
+                                                int64_t kp, const void *__restrict__ B0,
+                                                const void *__restrict__ B1, int64_t J0,
+                                                int64_t rowblk, GemmLds2 &L,
+                                                f32x16 (&acc)[2][4])
+{
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int lr = lane & 31, lh = lane >> 5;
+    constexpr bool kH = PREC == MFMA_BF16;
+    constexpr int kEl = kH ? 2 : 4;                 // bytes per element
+    constexpr int kPieceEl = 16 / kEl;              // elements per 16-byte piece
+    constexpr int kPR = kKC2 * kEl / 16;            // pieces per row and term
+    constexpr int kRow = kH ? kRow2h : kRow2f;
+#pragma unroll
+    for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+        for (int ct = 0; ct < 4; ++ct)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) acc[rt][ct][r] = 0.0f;
+    const int nchunks = (int)((kp + kKC2 - 1) / kKC2);
+    f32x4 ra[8], rb[4];  // staging registers (16 bytes each, reinterpreted)
+
+    // piece u of this thread: A pieces p = tid + 256 u (u < 8), B pieces likewise
+    auto load = [&](int c) {
+        const int64_t k0 = (int64_t)c * kKC2;
+        const int kc = (int)((kp - k0) < kKC2 ? (kp - k0) : kKC2);
+        const int vpr = kc * kEl / 16;  // valid pieces per row
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int p = tid + 256 * u;
+            const int term = kH ? p / (kTM * kPR) : 0;
+            const int q = p - term * kTM * kPR;
+            const int row = q / kPR, part = q - row * kPR;
+            if ((kH || p < kTM * kPR) && part < vpr) {
+                int64_t g = rowblk + row;
+                if (g > n - 1) g = n - 1;
+                const char *src = (const char *)(term ? A1 : A0) +
+                                  ((g * kp + k0) * kEl + part * 16);
+                ra[u] = *(const f32x4 *)src;
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int p = tid + 256 * u;
+            const int term = kH ? p / (kTN * kPR) : 0;
+            const int q = p - term * kTN * kPR;
+            const int row = q / kPR, part = q - row * kPR;
+            if ((kH || p < kTN * kPR) && part < vpr) {
+                const char *src = (const char *)(term ? B1 : B0) +
+                                  (((J0 + row) * kp + k0) * kEl + part * 16);
+                rb[u] = *(const f32x4 *)src;
+            }
+        }
+    };
+    auto store = [&](int c, int buf) {
+        const int64_t k0 = (int64_t)c * kKC2;
+        const int kc = (int)((kp - k0) < kKC2 ? (kp - k0) : kKC2);
+        const int vpr = kc * kEl / 16;
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int p = tid + 256 * u;
+            const int term = kH ? p / (kTM * kPR) : 0;
+            const int q = p - term * kTM * kPR;
+            const int row = q / kPR, part = q - row * kPR;
+            if ((kH || p < kTM * kPR) && part < vpr) {
+                char *dst = kH ? (char *)(L.h.a[buf][term] + row * kRow + part * kPieceEl)
+                               : (char *)(L.f.a[buf] + row * kRow + part * kPieceEl);
+                *(f32x4 *)dst = ra[u];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int p = tid + 256 * u;
+            const int term = kH ? p / (kTN * kPR) : 0;
+            const int q = p - term * kTN * kPR;
+            const int row = q / kPR, part = q - row * kPR;
+            if ((kH || p < kTN * kPR) && part < vpr) {
+                char *dst = kH ? (char *)(L.h.b[buf][term] + row * kRow + part * kPieceEl)
+                               : (char *)(L.f.b[buf] + row * kRow + part * kPieceEl);
+                *(f32x4 *)dst = rb[u];
+            }
+        }
+    };
+
+    load(0);
+    store(0, 0);
+    __syncthreads();
+    for (int c = 0; c < nchunks; ++c) {
+        const int buf = c & 1;
+        if (c + 1 < nchunks) load(c + 1);  // in flight during this chunk's MFMAs
+        const int64_t k0 = (int64_t)c * kKC2;
+        const int kc = (int)((kp - k0) < kKC2 ? (kp - k0) : kKC2);
+        if (kH) {
+            for (int kk = 0; kk < kc; kk += 16) {
+                bf16x8 ah[2], al[2];
+#pragma unroll
+                for (int rt = 0; rt < 2; ++rt) {
+                    const int row = wave * 64 + rt * 32 + lr;
+                    ah[rt] = *(const bf16x8 *)(L.h.a[buf][0] + row * kRow + kk + 8 * lh);
+                    al[rt] = *(const bf16x8 *)(L.h.a[buf][1] + row * kRow + kk + 8 * lh);
+                }
+#pragma unroll
+                for (int ct = 0; ct < 4; ++ct) {
+                    const int col = ct * 32 + lr;
+                    const bf16x8 bh = *(const bf16x8 *)(L.h.b[buf][0] + col * kRow + kk + 8 * lh);
+                    const bf16x8 bl = *(const bf16x8 *)(L.h.b[buf][1] + col * kRow + kk + 8 * lh);
+#pragma unroll
+                    for (int rt = 0; rt < 2; ++rt) {
+                        acc[rt][ct] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[rt], bh,
+                                                                              acc[rt][ct], 0, 0, 0);
+                        acc[rt][ct] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[rt], bl,
+                                                                              acc[rt][ct], 0, 0, 0);
+                        acc[rt][ct] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[rt], bh,
+                                                                              acc[rt][ct], 0, 0, 0);
+                    }
+                }
+            }
+        } else {
+            for (int kk = 0; kk < kc; kk += 8) {
+                f32x4 a[2];
+#pragma unroll
+                for (int rt = 0; rt < 2; ++rt) {
+                    const int row = wave * 64 + rt * 32 + lr;
+                    a[rt] = *(const f32x4 *)(L.f.a[buf] + row * kRow + kk + 4 * lh);
+                }
+#pragma unroll
+                for (int ct = 0; ct < 4; ++ct) {
+                    const int col = ct * 32 + lr;
+                    const f32x4 b = *(const f32x4 *)(L.f.b[buf] + col * kRow + kk + 4 * lh);
+#pragma unroll
+                    for (int rt = 0; rt < 2; ++rt) {
+                        acc[rt][ct] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[rt][0], b[0],
+                                                                           acc[rt][ct], 0, 0, 0);
+                        acc[rt][ct] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[rt][1], b[1],
+                                                                           acc[rt][ct], 0, 0, 0);
+                        acc[rt][ct] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[rt][2], b[2],
+                                                                           acc[rt][ct], 0, 0, 0);
+                        acc[rt][ct] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[rt][3], b[3],
+                                                                           acc[rt][ct], 0, 0, 0);
+                    }
+                }
+            }
+        }
+        if (c + 1 < nchunks) store(c + 1, buf ^ 1);  // the other buffer: free since the
+                                                     // barrier that ended chunk c - 1
+        __syncthreads();
+    }
+}
+
 template <int PREC, int EPI, int PF>
 __global__ __launch_bounds__(256) void k_gemm(
     const void *__restrict__ A0, const void *__restrict__ A1,
@@ -480,7 +659,8 @@ __global__ __launch_bounds__(256) void k_gemm(
     uint32_t *__restrict__ cnt, uint64_t *__restrict__ queue, uint32_t *__restrict__ qcount,
     uint64_t qcap, float *__restrict__ S)
 {
-    __shared__ GemmLds L;
+    using Lds = typename std::conditional<PF == 2, GemmLds2, GemmLds>::type;
+    __shared__ Lds L;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int lr = lane & 31, lh = lane >> 5;
     const int64_t J0 = (int64_t)blockIdx.x * kTN;
@@ -491,7 +671,9 @@ __global__ __launch_bounds__(256) void k_gemm(
     }
     f32x16 acc[2][4];
     // the block's barriers publish L.an
-    if (PF)
+    if constexpr (PF == 2)
+        gemm_block_pipe<PREC>(A0, A1, n, kp, B0, B1, J0, (int64_t)blockIdx.y * kTM, L, acc);
+    else if constexpr (PF == 1)
         gemm_block_chunk<PREC>(A0, A1, n, kp, B0, B1, J0, row0, L, acc);
     else
         gemm_block_steps<PREC>(A0, A1, n, kp, B0, B1, J0, row0, L, acc);
@@ -524,58 +706,81 @@ __global__ __launch_bounds__(256) void k_gemm(
 
     constexpr bool kPlain = PREC == MFMA_F32_PLAIN;
     const int rows_left = (int)(n - (int64_t)blockIdx.y * kTM);  // > 0
+    float cm[4];
+    bool jl[4];
 #pragma unroll
     for (int ct = 0; ct < 4; ++ct) {
         const int64_t J = J0 + ct * 32 + lr;
-        const bool jlive = J < ncols;
-        const float cm = (!kPlain && jlive) ? cmarg[J] : 0.0f;
-        uint32_t pos = 0, neg = 0, unc = 0;
+        jl[ct] = J < ncols;
+        cm[ct] = (!kPlain && jl[ct]) ? cmarg[J] : 0.0f;
+    }
+    // counts: per element one margin, two compares and two adds; rows past n
+    // occur in the last row block only (a uniform test per workgroup)
+    uint32_t pos[4] = {0u, 0u, 0u, 0u}, neg[4] = {0u, 0u, 0u, 0u};
+    auto count = [&](auto full) {
 #pragma unroll
         for (int rt = 0; rt < 2; ++rt)
 #pragma unroll
             for (int r = 0; r < 16; ++r) {
                 const int il = wave * 64 + rt * 32 + (r >> 2) * 8 + lh * 4 + (r & 3);
-                const bool live = jlive && il < rows_left;
-                const float v = acc[rt][ct][r];
-                if (kPlain) {
-                    // sign of t^ itself; zero counts on both sides
-                    pos += (live && v >= 0.0f) ? 1u : 0u;
-                    neg += (live && v <= 0.0f) ? 1u : 0u;
-                    continue;
+                const bool rl = decltype(full)::value || il < rows_left;
+                const float an_r = kPlain ? 0.0f : L.an[il];
+#pragma unroll
+                for (int ct = 0; ct < 4; ++ct) {
+                    const float v = acc[rt][ct][r];
+                    if (kPlain) {
+                        // sign of t^ itself; zero counts on both sides
+                        pos[ct] += (rl && v >= 0.0f) ? 1u : 0u;
+                        neg[ct] += (rl && v <= 0.0f) ? 1u : 0u;
+                    } else {
+                        const float marg = fmaf(kappa_a, an_r, cm[ct]);
+                        pos[ct] += (rl && v > marg) ? 1u : 0u;
+                        neg[ct] += (rl && v < -marg) ? 1u : 0u;
+                    }
                 }
-                const float marg = fmaf(kappa_a, L.an[il], cm);
-                const bool sp = v > marg, sn = v < -marg;
-                pos += (live && sp) ? 1u : 0u;
-                neg += (live && sn) ? 1u : 0u;
-                unc |= (live && !sp && !sn) ? (1u << (rt * 16 + r)) : 0u;
             }
-        if (!kPlain) L.unc[wave][ct][lane] = unc;
-        __builtin_amdgcn_sched_barrier(0);
-        // lanes l and l + 32 hold the same column
-        pos += (uint32_t)__shfl_xor((int)pos, 32);
-        neg += (uint32_t)__shfl_xor((int)neg, 32);
-        if (lh == 0) {
-            L.red[wave][ct * 32 + lr][0] = neg;  // t < 0: counts for "<= 0"
-            L.red[wave][ct * 32 + lr][1] = pos;  // t > 0: counts for ">= 0"
-        }
+    };
+    const bool rows_full = rows_left >= kTM;
+    if (rows_full)
+        count(std::true_type{});
+    else
+        count(std::false_type{});
+    int lrows = 32;  // this lane's live rows per column tile
+    if (!rows_full) {
+        lrows = 0;
+#pragma unroll
+        for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+            for (int r = 0; r < 16; ++r)
+                lrows += (wave * 64 + rt * 32 + (r >> 2) * 8 + lh * 4 + (r & 3)) < rows_left;
     }
-    if (!kPlain) {
-        // uncertain signs (rare): queue (query, direction, point)
-        for (int ct = 0; ct < 4; ++ct) {
-            uint32_t unc = L.unc[wave][ct][lane];
-            if (!unc) continue;
+#pragma unroll
+    for (int ct = 0; ct < 4; ++ct) {
+        if (!kPlain && jl[ct] && pos[ct] + neg[ct] < (uint32_t)lrows) {
+            // some sign of this column is uncertain (rare): queue (query,
+            // direction, point) for the binary64 recheck
             const int64_t J = J0 + ct * 32 + lr;
             const int64_t qi = J / m, j = J - qi * m;
-            while (unc) {
-                const int b = __builtin_ctz(unc);
-                unc &= unc - 1;
-                const int rt = b >> 4, r = b & 15;
-                const int64_t i = (int64_t)blockIdx.y * kTM + wave * 64 + rt * 32 + (r >> 2) * 8 +
-                                  lh * 4 + (r & 3);
-                const uint32_t slot = atomicAdd(qcount, 1u);
-                if ((uint64_t)slot < qcap)
-                    queue[slot] = ((uint64_t)qi << 48) | ((uint64_t)j << 32) | (uint64_t)i;
-            }
+            for (int rt = 0; rt < 2; ++rt)
+                for (int r = 0; r < 16; ++r) {
+                    const int il = wave * 64 + rt * 32 + (r >> 2) * 8 + lh * 4 + (r & 3);
+                    if (il >= rows_left) continue;
+                    const float v = acc[rt][ct][r];
+                    const float marg = fmaf(kappa_a, L.an[il], cm[ct]);
+                    if (v > marg || v < -marg) continue;
+                    const int64_t i = (int64_t)blockIdx.y * kTM + il;
+                    const uint32_t slot = atomicAdd(qcount, 1u);
+                    if ((uint64_t)slot < qcap)
+                        queue[slot] = ((uint64_t)qi << 48) | ((uint64_t)j << 32) | (uint64_t)i;
+                }
+        }
+        uint32_t pc = jl[ct] ? pos[ct] : 0u, nc = jl[ct] ? neg[ct] : 0u;
+        // lanes l and l + 32 hold the same column
+        pc += (uint32_t)__shfl_xor((int)pc, 32);
+        nc += (uint32_t)__shfl_xor((int)nc, 32);
+        if (lh == 0) {
+            L.red[wave][ct * 32 + lr][0] = nc;  // t < 0: counts for "<= 0"
+            L.red[wave][ct * 32 + lr][1] = pc;  // t > 0: counts for ">= 0"
         }
     }
     __syncthreads();
@@ -722,7 +927,7 @@ int64_t mfma_col_pad(int64_t ncols) { return (ncols + kTN - 1) / kTN * kTN; }
 
 namespace {
 
-constexpr int kVariants = 2;
+constexpr int kVariants = 3;
 
 // Launch of one GEMM variant (PF = variant) for either epilogue.
 struct GemmLaunch {
@@ -765,7 +970,9 @@ struct GemmLaunch {
     }
     hipError_t run(int v, hipStream_t st) const
     {
-        if (v == 1)
+        if (v == 2)
+            go_v<2>(st);
+        else if (v == 1)
             go_v<1>(st);
         else
             go_v<0>(st);
