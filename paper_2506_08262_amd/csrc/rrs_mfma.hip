@@ -214,7 +214,7 @@ constexpr int kTM = 256, kTN = 128, kKC = 64;
 constexpr int kLdsRow16 = kKC + 8;   // bf16 elements per staged B row (padded)
 constexpr int kLdsRow32 = kKC + 4;   // binary32 elements per staged B row (padded)
 
-struct GemmLds {
+struct alignas(16) GemmLds {
     union {
         __bf16 bh[kTN * kLdsRow16 * 2];  // hi rows, then lo rows
         float bf[kTN * kLdsRow32];
@@ -231,7 +231,7 @@ constexpr int kRow2h = kKC2 + 8;   // bf16 elements per staged row (80 B: 8-lane
                                    // distinct 16-byte bank groups)
 constexpr int kRow2f = kKC2 + 4;   // binary32 elements per staged row (144 B)
 
-struct GemmLds2 {
+struct alignas(16) GemmLds2 {
     union {
         struct {
             __bf16 a[2][2][kTM * kRow2h];  // [buffer][term]

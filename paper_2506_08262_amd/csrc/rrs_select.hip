@@ -45,7 +45,7 @@ constexpr int kCapA = 256;     // collected values of the target's bin (one per 
 constexpr int kCapB = 64;      // collected values of the next bin (pairs)
 constexpr int kRadixCand = 64;
 
-struct RegShared {
+struct alignas(16) RegShared {
     uint32_t hist[kBins + 64];  // 256 bins, then one dummy slot per lane
     uint32_t skey[64];          // sampled keys
     uint32_t srank[64];         // their ranks

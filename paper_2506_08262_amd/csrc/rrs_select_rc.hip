@@ -9,13 +9,15 @@
 //
 // One order statistic of rank k (or the pair k, k + 1):
 //   1. 64 sampled approximations bracket the rank; one pass over the column
-//      counts the approximations below the bracket and bins the rest (as in
-//      the exact selects);
+//      bins the approximations linearly over the bracket (256 bins of a
+//      power-of-two width, one fma and a clamp per value), with the values
+//      below and above the bracket counted in per-lane slots at either end;
 //   2. the bins holding ranks k, k + 1 span approximations [vlo, vhi], so the
 //      exact statistics lie in [vlo - E, vhi + E] (shifted by c); every point
 //      whose approximation is below vlo - 2E is exactly below them, every one
-//      above vhi + 2E exactly above.  A second pass counts the points below
-//      that window (B) and collects the indices inside it;
+//      above vhi + 2E exactly above.  A second pass collects the indices
+//      inside that window; the points below it (B) are those of the bins
+//      below the target ones, less the candidates among them;
 //   3. those candidates are recomputed with the binary64 recipe and ranked
 //      exactly: the statistics are the candidates of ranks k - B, k + 1 - B.
 // MAD (projection depth) is the same select on |s_i - (med + c)| with the
@@ -50,15 +52,20 @@ constexpr int kRadixCand = 64;
 constexpr int kUnroll = 4;
 constexpr int kDs = 128;         // coordinates kept in LDS for the recomputation
 
-struct RcShared {
-    uint32_t hist[kBins + 64];   // 256 bins, then one dummy slot per lane
+// Histogram layout: 64 per-lane slots for values below the bracket, the 256
+// bins, 64 per-lane slots for values above it.
+constexpr int kHistLo = 64, kHistN = kHistLo + kBins + 64;
+
+struct alignas(16) RcShared {
+    uint32_t hist[kHistN];
     uint32_t skey[64];
     uint32_t srank[64];
     float sval[64];
     uint32_t cidx[kCapW];
     double cval[kCapW];
-    uint32_t Lk, R, sh, tau;
-    uint32_t below, ncand;
+    float scale, off;            // bins of the current bracket
+    uint32_t kmin, kmax;         // order keys of the column's range
+    uint32_t below, ncand, nlow, beforeA;
     uint32_t binA, binB;
     int32_t fast;
     uint32_t count;
@@ -80,6 +87,7 @@ struct Col {
     const double *z;   // [d] query (LDS copy when d <= kDs)
     const double *u;   // [d] direction j, unit stride (LDS copy when d <= kDs)
     int64_t ustride;   // stride of u: 1 for the LDS copy, ldm in global memory
+    bool sane;         // binary32 projections finite with room to spare
 };
 
 // The recipe's projection of point i (EXACT), or the binary32 one shifted.
@@ -129,22 +137,56 @@ __device__ __forceinline__ bool fkey_finite(uint32_t k)
     return PH == 0 ? k < 0xFF800000u : k < 0x7F800000u;
 }
 
-// Bracket key on binary32 bits with magnitudes below tau (>= 1) collapsed
-// onto the key of zero (as bin_key does on binary64 high words); monotone in
-// x.  With e = max(mag - (tau - 1), 0) (0 for collapsed magnitudes, else
-// 1 + mag - tau): phase 0 keys are 2^31 + e for x >= 0 and 2^31 - e for
-// x < 0; phase 1 keys (x >= 0) are e.  taum1 = tau - 1.
-template <int PH>
-__device__ __forceinline__ uint32_t fbin_key(float x, uint32_t taum1)
+// Linear bins over a value bracket.  t = fma(x, scale, off) rounds once, so
+// it is monotone in x; bin = floor(t) for t in [0, 256).  The clamp limits
+// differ per lane (lo = -(lane + 1), hi = 256 + lane), so values outside the
+// bracket land in per-lane slots hist[kHistLo + floor(clamped t)] at either
+// end of the histogram instead of piling onto one counter.
+__device__ __forceinline__ int lin_slot(float x, float scale, float off, float lo, float hi)
 {
-    const uint32_t b = __float_as_uint(x);
-    if (PH == 0) {
-        const uint32_t mag = b & 0x7FFFFFFFu;
-        const uint32_t e = (mag > taum1 ? mag : taum1) - taum1;
-        const uint32_t sgn = (uint32_t)((int32_t)b >> 31);  // 0 or all ones
-        return 0x80000000u + ((e ^ sgn) - sgn);
+    return (int)floorf(__builtin_amdgcn_fmed3f(fmaf(x, scale, off), lo, hi));
+}
+
+// Bins for the bracket [L, H]: scale = 2^e with (H - L) scale <= 255 and
+// max(|L|, |H|) scale < 2^38, off = -L scale.
+__device__ void lin_fit(float L, float H, float &scale, float &off)
+{
+    const double w = (double)H - (double)L;
+    const double M = fmax(fabs((double)L), fabs((double)H));
+    int e = 0;
+    if (w > 0.0) e = ilogb(255.0 / w);
+    if (M > 0.0) {
+        const int em = 37 - ilogb(M);
+        if (w <= 0.0 || em < e) e = em;
     }
-    return (b > taum1 ? b : taum1) - taum1;
+    e = e < -126 ? -126 : (e > 126 ? 126 : e);
+    scale = ldexpf(1.0f, e);
+    off = -L * scale;
+}
+
+// Value bounds of bins 0 <= b <= 255: a value in bin b or above satisfies
+// x >= lin_lo(b), one in bin b or below x <= lin_hi(b).  t >= b forces
+// x scale + off >= b - 2^-17 (half the float spacing below 256), t < b + 1
+// forces it below b + 1 + 2^-16; the binary64 evaluation is widened by a
+// relative 2^-50 and the division by a power of two is exact.
+__device__ __forceinline__ double lin_lo(uint32_t b, float scale, float off)
+{
+    const double r = ((double)b - 0x1p-14) - (double)off;
+    return (r - fabs(r) * 0x1p-50) / (double)scale;
+}
+
+__device__ __forceinline__ double lin_hi(uint32_t b, float scale, float off)
+{
+    const double r = ((double)b + 1.0 + 0x1p-14) - (double)off;
+    return (r + fabs(r) * 0x1p-50) / (double)scale;
+}
+
+// Inverse of fkey32 for finite keys.
+template <int PH>
+__device__ __forceinline__ float fkey_value(uint32_t k)
+{
+    if (PH == 0) return __uint_as_float(k >= 0x80000000u ? k ^ 0x80000000u : ~k);
+    return __uint_as_float(k);
 }
 
 __device__ __forceinline__ float lane_bcast_f(float x, int src)
@@ -159,35 +201,10 @@ __device__ __forceinline__ double exact_v(double t, double med)
     return PH == 0 ? t : fabs(t - med);
 }
 
-__device__ __forceinline__ double bits_value(uint32_t b) { return (double)__uint_as_float(b); }
-
-// Bounds of the binary32 values whose fbin_key<PH>(., tau) is K: every key
-// outside the collapsed neighbourhood of zero is one value, the collapsed key
-// holds the magnitudes below tau.
-template <int PH>
-__device__ __forceinline__ double key_lo_value(uint32_t K, uint32_t tau)
-{
-    if (PH == 0) {
-        if (K > 0x80000000u) return bits_value(K - 0x80000001u + tau);
-        if (K == 0x80000000u) return -bits_value(tau);
-        return -bits_value(0x7FFFFFFFu - K + tau);
-    }
-    return K == 0u ? 0.0 : bits_value(K - 1u + tau);
-}
-
-template <int PH>
-__device__ __forceinline__ double key_hi_value(uint32_t K, uint32_t tau)
-{
-    if (PH == 0) {
-        if (K > 0x80000000u) return bits_value(K - 0x80000001u + tau);
-        if (K == 0x80000000u) return bits_value(tau);
-        return -bits_value(0x7FFFFFFFu - K + tau);
-    }
-    return K == 0u ? bits_value(tau) : bits_value(K - 1u + tau);
-}
-
-// Where a select reads the column's binary32 projections from.
-// StreamSrc: global memory, 4 loads in flight per lane (any n).
+// Where a select reads the column's binary32 projections from.  Both hand
+// every slot to f(i, s_i); slots past n read +inf, which every pass treats as
+// above the bracket and outside the window (live values are finite).
+// StreamSrc: global memory, 4 loads in flight per lane (any n < 2^31).
 struct StreamSrc {
     static constexpr int kMaxLevel = 6;  // rebracket / narrowing passes allowed
     const float *s;
@@ -199,26 +216,23 @@ struct StreamSrc {
     template <class F>
     __device__ __forceinline__ void each(F &&f) const
     {
-        for (int64_t i0 = threadIdx.x; i0 < n; i0 += (int64_t)kUnroll * kT) {
+        const int nn = (int)n;
+        for (int i0 = threadIdx.x; i0 < nn; i0 += kUnroll * kT) {
             float t[kUnroll];
 #pragma unroll
             for (int u = 0; u < kUnroll; ++u) {
-                const int64_t i = i0 + (int64_t)u * kT;
-                t[u] = i < n ? s[i] : 0.0f;
+                const int i = i0 + u * kT;
+                t[u] = i < nn ? s[i] : __builtin_inff();
             }
 #pragma unroll
-            for (int u = 0; u < kUnroll; ++u) {
-                const int64_t i = i0 + (int64_t)u * kT;
-                f(i, t[u], i < n);
-            }
+            for (int u = 0; u < kUnroll; ++u) f(i0 + u * kT, t[u]);
         }
     }
 };
 
 // RegSrc: the column held in registers, VPT values per lane (entry
-// threadIdx.x + kT v in slot v; slots past n are never live).  Every loop
-// over the slots is unrolled with compile-time indices, which keeps the
-// array in registers.
+// threadIdx.x + kT v in slot v, +inf past n).  Every loop over the slots is
+// unrolled with compile-time indices, which keeps the array in registers.
 template <int VPT>
 struct RegSrc {
     static constexpr int kMaxLevel = 0;  // short columns: one pass, misses fall back
@@ -236,17 +250,15 @@ struct RegSrc {
     template <class F>
     __device__ __forceinline__ void each(F &&f) const
     {
-        // opaque registers: values derived in an earlier pass (binary64
-        // conversions, keys) are recomputed instead of being kept live
+        // opaque registers: values derived in an earlier pass are recomputed
+        // instead of being kept live
 #pragma unroll
         for (int u = 0; u < VPT; ++u) asm volatile("" : "+v"(v[u]));
-        // slots below n / kT are full for every lane (a scalar test)
-        const int nfull = (int)(n / kT);
+        // likewise the slot indices (only the rare candidates use them)
+        int base = (int)threadIdx.x;
+        asm volatile("" : "+v"(base));
 #pragma unroll
-        for (int u = 0; u < VPT; ++u) {
-            const int64_t i = (int64_t)threadIdx.x + (int64_t)kT * u;
-            f(i, v[u], u < nfull || i < n);
-        }
+        for (int u = 0; u < VPT; ++u) f(base + kT * u, v[u]);
     }
 };
 
@@ -395,119 +407,146 @@ __device__ uint64_t rc_radix_next(const Col &C, double med, uint64_t k, uint64_t
     return res;
 }
 
+// Smallest and largest finite approximation of the column in phase PH (as
+// floats); false when there is none.
+template <int PH, class SRC>
+__device__ bool rc_range(const SRC &src, float sigf, RcShared &sh, float &L, float &H)
+{
+    const int lane = threadIdx.x & 63;
+    if (threadIdx.x == 0) {
+        sh.kmin = 0xFFFFFFFFu;
+        sh.kmax = 0u;
+    }
+    __syncthreads();
+    uint32_t kmin = 0xFFFFFFFFu, kmax = 0u;
+    src.each([&](int, float sv) {
+        const uint32_t kx = fkey32<PH>(approx_v<PH>(sv, sigf));
+        if (fkey_finite<PH>(kx)) {
+            kmin = kx < kmin ? kx : kmin;
+            kmax = kx > kmax ? kx : kmax;
+        }
+    });
+    for (int o = 32; o > 0; o >>= 1) {
+        const uint32_t a = (uint32_t)__shfl_xor((int)kmin, o);
+        const uint32_t b = (uint32_t)__shfl_xor((int)kmax, o);
+        kmin = a < kmin ? a : kmin;
+        kmax = b > kmax ? b : kmax;
+    }
+    if (lane == 0) {
+        atomicMin(&sh.kmin, kmin);
+        atomicMax(&sh.kmax, kmax);
+    }
+    __syncthreads();
+    const uint32_t a = sh.kmin, b = sh.kmax;
+    __syncthreads();
+    if (a > b) return false;
+    L = fkey_value<PH>(a);
+    H = fkey_value<PH>(b);
+    return true;
+}
+
 // The exact values of ranks k (and k + 1 if pair) in phase PH.  Returns true
 // when the window path served them; then sh.cval[0 .. ncand) holds the
 // window's exact values and *below the number of points under the window.
 template <int PH, bool EXACT, class SRC>
-__device__ bool rc_select(const Col &C, const SRC &src, double med, double sig, double E,
+__device__ __forceinline__ bool rc_select(const Col &C, const SRC &src, double med, double sig, double E,
                           uint64_t k, bool pair, double &a, double &b, uint64_t *below,
                           RcShared &sh, uint32_t *stats)
 {
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int64_t n = C.n;
     const float sigf = (float)sig;
-    sh.hist[tid] = 0;
-    if (tid < 64) sh.srank[tid] = 0;
-    if (tid == 0) {
-        sh.below = 0;
-        sh.ncand = 0;
-    }
-    // 64 sampled approximations: slot 16 w + l from lane l < 16 of wave w
-    if (lane < 16) {
-        const int slot = wave * 16 + lane;
-        const float x = approx_v<PH>(src.sample(slot), sigf);
-        const uint32_t kx = fkey32<PH>(x);
-        sh.skey[slot] = fkey_finite<PH>(kx) ? kx : 0xFFFFFFFFu;
-        sh.sval[slot] = x;
-    }
-    __syncthreads();
-    {
-        const uint32_t mine = sh.skey[lane];
-        uint32_t part = 0;
-#pragma unroll
-        for (int jj = 0; jj < 16; ++jj) {
-            const int o = wave * 16 + jj;
-            const uint32_t ko = sh.skey[o];
-            part += (ko < mine || (ko == mine && o < lane)) ? 1u : 0u;
-        }
-        atomicAdd(&sh.srank[lane], part);
-    }
-    __syncthreads();
-    if (tid < 64) {
-        const uint32_t kx = sh.skey[lane];
-        const bool ok = kx != 0xFFFFFFFFu;
-        const uint32_t rank = sh.srank[lane];
-        const uint32_t S = (uint32_t)__popcll(__ballot(ok));
-        int fast0 = S >= 16 ? 1 : 0;
-        uint32_t Lk = 0, Hk = 0, tau = 0;
-        if (fast0) {
-            const double f = ((double)k + 0.5) / (double)n;
-            const double pos = f * (double)S;
-            const double del = 2.5 * sqrt((double)S * f * (1.0 - f)) + 1.5;
-            double lo = floor(pos - del), hi = ceil(pos + del + (pair ? 1.0 : 0.0));
-            if (lo < 0.0) lo = 0.0;
-            if (hi > (double)(S - 1)) hi = (double)(S - 1);
-            const uint32_t rlo = (uint32_t)lo, rhi = (uint32_t)hi;
-            const uint64_t mlo = __ballot(ok && rank == rlo), mhi = __ballot(ok && rank == rhi);
-            const float xv = sh.sval[lane];
-            const float L = lane_bcast_f(xv, __ffsll((long long)mlo) - 1);
-            const float H = lane_bcast_f(xv, __ffsll((long long)mhi) - 1);
-            tau = __float_as_uint(fmaxf(fabsf(L), fabsf(H)) * 0x1p-6f) & 0x7FFFFFFFu;
-            if (tau < 1u) tau = 1u;
-            Lk = fbin_key<PH>(L, tau - 1u);
-            Hk = fbin_key<PH>(H, tau - 1u);
-        }
-        if (lane == 0) {
-            const uint32_t R = Hk - Lk;
-            const uint32_t nb = 32u - (uint32_t)__clz((int)(R | 1u));
-            sh.Lk = Lk;
-            sh.R = R;
-            sh.sh = nb > 8u ? nb - 8u : 0u;
-            sh.tau = tau;
-            sh.fast = fast0;
-        }
-    }
-    __syncthreads();
-    // register-resident columns keep a single pass (a miss falls back);
-    // streamed columns rebracket and narrow instead
-    bool fast = SRC::kMaxLevel > 0 || sh.fast != 0;
+    bool fast = C.sane;
     if (fast) {
-        // the sampled bracket, or the whole key range when too few samples
-        // took part
-        uint32_t Lk = sh.Lk, R = sh.R, bsh = sh.sh;
-        const uint32_t tau = sh.tau;
-        if (SRC::kMaxLevel > 0 && sh.fast == 0) {
-            Lk = 0u;
-            R = 0xFFFFFFFFu;
-            bsh = 24u;
+        sh.hist[tid] = 0;
+        if (tid < kHistN - kT) sh.hist[kT + tid] = 0;
+        if (tid < 64) sh.srank[tid] = 0;
+        // 64 sampled approximations: slot 16 w + l from lane l < 16 of wave w
+        if (lane < 16) {
+            const int slot = wave * 16 + lane;
+            const float x = approx_v<PH>(src.sample(slot), sigf);
+            const uint32_t kx = fkey32<PH>(x);
+            sh.skey[slot] = fkey_finite<PH>(kx) ? kx : 0xFFFFFFFFu;
+            sh.sval[slot] = x;
         }
-        uint32_t nbelow = 0;
-        const uint32_t dummy = (uint32_t)kBins + (uint32_t)lane;
+        __syncthreads();
+        {
+            const uint32_t mine = sh.skey[lane];
+            uint32_t part = 0;
+#pragma unroll
+            for (int jj = 0; jj < 16; ++jj) {
+                const int o = wave * 16 + jj;
+                const uint32_t ko = sh.skey[o];
+                part += (ko < mine || (ko == mine && o < lane)) ? 1u : 0u;
+            }
+            atomicAdd(&sh.srank[lane], part);
+        }
+        __syncthreads();
+        if (tid < 64) {
+            const uint32_t kx = sh.skey[lane];
+            const bool ok = kx != 0xFFFFFFFFu;
+            const uint32_t rank = sh.srank[lane];
+            const uint32_t S = (uint32_t)__popcll(__ballot(ok));
+            const int fast0 = S >= 16 ? 1 : 0;
+            float scale = 1.0f, off = 0.0f;
+            if (fast0) {
+                const double f = ((double)k + 0.5) / (double)n;
+                const double pos = f * (double)S;
+                const double del = 2.5 * sqrt((double)S * f * (1.0 - f)) + 1.5;
+                double lo = floor(pos - del), hi = ceil(pos + del + (pair ? 1.0 : 0.0));
+                if (lo < 0.0) lo = 0.0;
+                if (hi > (double)(S - 1)) hi = (double)(S - 1);
+                const uint32_t rlo = (uint32_t)lo, rhi = (uint32_t)hi;
+                const uint64_t mlo = __ballot(ok && rank == rlo), mhi = __ballot(ok && rank == rhi);
+                const float xv = sh.sval[lane];
+                const float L = lane_bcast_f(xv, __ffsll((long long)mlo) - 1);
+                const float H = lane_bcast_f(xv, __ffsll((long long)mhi) - 1);
+                lin_fit(L, H, scale, off);
+            }
+            if (lane == 0) {
+                sh.scale = scale;
+                sh.off = off;
+                sh.fast = fast0;
+            }
+        }
+        __syncthreads();
+        // register-resident columns keep a single pass (a miss falls back);
+        // streamed columns rebracket and narrow instead
+        fast = SRC::kMaxLevel > 0 || sh.fast != 0;
+    }
+    if (fast) {
+        float scale = sh.scale, off = sh.off;
+        bool whole = false;
+        if (SRC::kMaxLevel > 0 && sh.fast == 0) {
+            // too few samples took part: bracket the whole column
+            float L, H;
+            fast = rc_range<PH>(src, sigf, sh, L, H);
+            if (fast) lin_fit(L, H, scale, off);
+            whole = true;
+        }
+        // per-lane clamp limits: slots 63 - lane (below) and 320 + lane (above)
+        const float lo_l = -(float)(lane + 1), hi_l = (float)(kBins + lane);
+        uint32_t *const bins = sh.hist + kHistLo;
         // histogram passes: the first bins the bracket; while the target bins
         // hold more than half the candidate room (long columns), the next pass
-        // bins just those bins 256 times finer
-        for (int level = 0;; ++level) {
-            nbelow = 0;
-            // bins 0..255 cover keys Lk .. Lk + (256 << bsh) - 1 (at least the
-            // bracket); keys outside go to the lane's dummy slot
-            src.each([&](int64_t, float sv, bool live) {
-                const uint32_t kx = fbin_key<PH>(approx_v<PH>(sv, sigf), tau - 1u);
-                const uint32_t dk = kx - Lk;
-                nbelow += (live && kx < Lk) ? 1u : 0u;
-                const uint32_t bin = dk >> bsh;
-                atomicAdd(&sh.hist[live ? (bin < dummy ? bin : dummy) : dummy], 1u);
+        // bins just those bins at least twice finer
+        for (int level = 0; fast; ++level) {
+            src.each([&](int, float sv) {
+                const int t = lin_slot(approx_v<PH>(sv, sigf), scale, off, lo_l, hi_l);
+                atomicAdd(&bins[t], 1u);
             });
-            for (int off = 32; off > 0; off >>= 1)
-                nbelow += (uint32_t)__shfl_xor((int)nbelow, off);
-            if (lane == 0 && nbelow) atomicAdd(&sh.below, nbelow);
             __syncthreads();
             if (tid < 64) {
-                const uint64_t base = sh.below;
+                uint32_t lo = sh.hist[lane];  // the below slots
+                for (int o = 32; o > 0; o >>= 1) lo += (uint32_t)__shfl_xor((int)lo, o);
                 uint32_t bA, rA, cA, bB, rB, cB;
                 bool fA, fB;
-                scan_hist(sh.hist, base, k, bA, rA, cA, fA);
-                scan_hist(sh.hist, base, k + 1, bB, rB, cB, fB);
-                if (fA) sh.binA = bA;
+                scan_hist(bins, lo, k, bA, rA, cA, fA);
+                scan_hist(bins, lo, k + 1, bB, rB, cB, fB);
+                if (fA) {
+                    sh.binA = bA;
+                    sh.beforeA = (uint32_t)(k - rA);
+                }
                 if (fB) sh.binB = bB;
                 const uint64_t ma = __ballot(fA), mb = __ballot(fB);
                 if (lane == 0) sh.fast = (ma != 0 && (!pair || mb != 0)) ? 1 : 0;
@@ -515,64 +554,82 @@ __device__ bool rc_select(const Col &C, const SRC &src, double med, double sig, 
             __syncthreads();
             fast = sh.fast != 0;
             if (level >= SRC::kMaxLevel) break;
+            float L, H;
+            bool rebracket = false;
             if (!fast) {
-                // the sampled bracket missed the rank: bin the whole key range
-                // instead (then narrow as usual)
-                if (level > 0 || (Lk == 0u && R == 0xFFFFFFFFu)) break;
-                Lk = 0u;
-                R = 0xFFFFFFFFu;
-                bsh = 24u;
+                // the sampled bracket missed the rank: bracket the whole
+                // column instead (then narrow as usual)
+                if (whole) break;
+                fast = rc_range<PH>(src, sigf, sh, L, H);
+                if (!fast) break;
+                whole = rebracket = true;
             } else {
                 const uint32_t bA = sh.binA, bB = pair ? sh.binB : sh.binA;
                 uint32_t held = 0;
-                for (uint32_t b = bA; b <= bB; ++b) held += sh.hist[b];
-                if (held <= (uint32_t)kCapW / 2 || bsh == 0) break;
-                // narrow to the target bins and start over
-                Lk = Lk + (bA << bsh);
-                R = ((bB - bA + 1) << bsh) - 1;
-                const uint32_t nb = 32u - (uint32_t)__clz((int)(R | 1u));
-                bsh = nb > 8u ? nb - 8u : 0u;
+                for (uint32_t x = bA; x <= bB; ++x) held += bins[x];
+                if (held <= (uint32_t)kCapW / 2) break;
+                // narrow to the target bins
+                L = __double2float_rd(lin_lo(bA, scale, off));
+                H = __double2float_ru(lin_hi(bB, scale, off));
             }
+            float ns, no;
+            lin_fit(L, H, ns, no);
+            if (!rebracket && !(ns > scale)) break;  // no finer bins to be had
+            scale = ns;
+            off = no;
             __syncthreads();
             sh.hist[tid] = 0;
-            if (tid == 0) sh.below = 0;
+            if (tid < kHistN - kT) sh.hist[kT + tid] = 0;
             __syncthreads();
         }
         if (fast) {
             const uint32_t bA = sh.binA, bB = pair ? sh.binB : sh.binA;
             // approximations of the target bins lie in [vlo, vhi]
-            const uint64_t klo = (uint64_t)Lk + ((uint64_t)bA << bsh);
-            uint64_t khi = (uint64_t)Lk + (((uint64_t)bB + 1) << bsh) - 1;
-            if (khi > 0xFFFFFFFFull) khi = 0xFFFFFFFFull;
-            const double vlo = key_lo_value<PH>((uint32_t)klo, tau);
-            const double vhi = key_hi_value<PH>((uint32_t)khi, tau);
+            const double vlo = lin_lo(bA, scale, off), vhi = lin_hi(bB, scale, off);
             // phase 1 adds the roundings of sig to binary32 and of s - sig
             const double Ew = PH == 0 ? E : E * 1.000001 + 0x1p-22 * (fabs(sig) + fabs(vlo) +
                                                                       fabs(vhi) + E) + 1e-300;
-            // the window, rounded outwards to binary32
-            const float wlo = __double2float_rd(vlo - 2.0 * Ew);
-            const float whi = __double2float_ru(vhi + 2.0 * Ew);
-            if (tid == 0) sh.below = 0;
+            // the window [wlo, whi] as |x - mid| <= hw, evaluated in binary32
+            // with the roundings of mid, hw and x - mid absorbed into hwf
+            const double wlo = vlo - 2.0 * Ew, whi = vhi + 2.0 * Ew;
+            const double mid = 0.5 * (wlo + whi);
+            const float midf = (float)mid;
+            const double hw = fmax(mid - wlo, whi - mid) * (1.0 + 0x1p-50);
+            const float hwf =
+                __double2float_ru((hw + fabs(mid - (double)midf)) * (1.0 + 0x1p-50));
+            const float fA = (float)bA;
+            if (tid == 0) {
+                sh.ncand = 0;
+                sh.nlow = 0;
+            }
             __syncthreads();
-            nbelow = 0;
-            src.each([&](int64_t i, float sv, bool live) {
+            src.each([&](int i, float sv) {
                 const float x = approx_v<PH>(sv, sigf);
-                nbelow += (live && x < wlo) ? 1u : 0u;
-                if (live && x >= wlo && x <= whi) {
+                if (fabsf(x - midf) <= hwf) {
+                    // flag the candidates binned below bin A (t < bA is the
+                    // histogram pass's test, the same fma)
+                    const uint32_t low = fmaf(x, scale, off) < fA ? 0x80000000u : 0u;
                     const uint32_t p = atomicAdd(&sh.ncand, 1u);
-                    if (p < (uint32_t)kCapW) sh.cidx[p] = (uint32_t)i;
+                    if (p < (uint32_t)kCapW) sh.cidx[p] = (uint32_t)i | low;
                 }
             });
-            for (int off = 32; off > 0; off >>= 1)
-                nbelow += (uint32_t)__shfl_xor((int)nbelow, off);
-            if (lane == 0 && nbelow) atomicAdd(&sh.below, nbelow);
             __syncthreads();
             const uint32_t nc = sh.ncand;
-            const uint64_t B = sh.below;
+            if (nc <= (uint32_t)kCapW) {
+                uint32_t low = 0;
+                for (uint32_t p = tid; p < nc; p += kT) low += sh.cidx[p] >> 31;
+                for (int o = 32; o > 0; o >>= 1) low += (uint32_t)__shfl_xor((int)low, o);
+                if (lane == 0 && low) atomicAdd(&sh.nlow, low);
+            }
+            __syncthreads();
+            // points below the window: those binned below bin A that are not
+            // candidates (a non-candidate under bin A lies below wlo)
+            const uint64_t B = (uint64_t)sh.beforeA - sh.nlow;
             fast = nc <= (uint32_t)kCapW && B <= k && k + (pair ? 1 : 0) < B + nc;
             if (fast) {
                 for (uint32_t p = tid; p < nc; p += kT)
-                    sh.cval[p] = exact_v<PH>(exact_t<EXACT>(C, (int64_t)sh.cidx[p]), med);
+                    sh.cval[p] = exact_v<PH>(
+                        exact_t<EXACT>(C, (int64_t)(sh.cidx[p] & 0x7FFFFFFFu)), med);
                 __syncthreads();
                 const uint64_t rA = k - B, rB = k + 1 - B;
                 if (nc <= (uint32_t)kQuad) {
@@ -600,7 +657,7 @@ __device__ bool rc_select(const Col &C, const SRC &src, double med, double sig, 
         }
     }
     __syncthreads();
-    if (SRC::kMaxLevel == 0) {
+    if (SRC::kMaxLevel == 0 && C.sane) {
         // a register-resident column that missed: the streamed select over
         // the same column in global memory (rebracketing, narrowing)
         return rc_select<PH, EXACT>(C, StreamSrc{C.s, C.n}, med, sig, E, k, pair, a, b, below,
@@ -617,7 +674,7 @@ __device__ bool rc_select(const Col &C, const SRC &src, double med, double sig, 
 // Number of points with t <= med: from the median's window when it served,
 // else by a counting pass over recomputed values.
 template <bool EXACT>
-__device__ uint64_t rc_count_le(const Col &C, double med, bool window, uint64_t below,
+__device__ __forceinline__ uint64_t rc_count_le(const Col &C, double med, bool window, uint64_t below,
                                 RcShared &sh)
 {
     const int tid = threadIdx.x, lane = tid & 63;
@@ -693,7 +750,12 @@ __global__ __launch_bounds__(kT) void k_select_rc(const float *__restrict__ S, i
     C.s = S + (qi * m + j) * n;
     C.n = n;
     C.c = cq[qi * m + j];
-    C.E = EXACT ? eq[qi * m + j] : 0.0;
+    {
+        // eq is +inf or NaN when the data's norm bound is out of range
+        const double e = eq[qi * m + j];
+        C.sane = e < 0x1p100;
+        C.E = EXACT ? e : 0.0;
+    }
     C.X = X;
     C.d = d;
     if (EXACT && d <= kDs) {
@@ -719,7 +781,7 @@ __global__ __launch_bounds__(kT) void k_select_rc(const float *__restrict__ S, i
 #pragma unroll
         for (int u = 0; u < V; ++u) {
             const int64_t i = (int64_t)threadIdx.x + (int64_t)kT * u;
-            v[u] = i < n ? C.s[i] : 0.0f;
+            v[u] = i < n ? C.s[i] : __builtin_inff();
         }
         D = rc_depth<NOTION, EXACT>(C, RegSrc<V>{v, n}, sh, stats);
     }
