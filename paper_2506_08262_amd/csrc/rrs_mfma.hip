@@ -214,10 +214,13 @@ constexpr int kTM = 256, kTN = 128, kKC = 64;
 constexpr int kLdsRow16 = kKC + 8;   // bf16 elements per staged B row (padded)
 constexpr int kLdsRow32 = kKC + 4;   // binary32 elements per staged B row (padded)
 
+constexpr int kStg = 64 + 4;          // floats per staged column in the store epilogue
+
 struct alignas(16) GemmLds {
     union {
         __bf16 bh[kTN * kLdsRow16 * 2];  // hi rows, then lo rows
         float bf[kTN * kLdsRow32];
+        float stg[4 * 32 * kStg];        // store epilogue: per wave 32 columns x 64 rows
     };
     uint32_t red[4][kTN][2];
     float an[kTM];   // norm bounds of the tile's points (sign epilogue)
@@ -241,6 +244,7 @@ struct alignas(16) GemmLds2 {
             float a[2][kTM * kRow2f];
             float b[2][kTN * kRow2f];
         } f;
+        float stg[4 * 32 * kStg];  // store epilogue (as in GemmLds)
     };
     uint32_t red[4][kTN][2];
     float an[kTM];
@@ -679,6 +683,36 @@ __global__ __launch_bounds__(256) void k_gemm(
         gemm_block_steps<PREC>(A0, A1, n, kp, B0, B1, J0, row0, L, acc);
 
     if (EPI == EPI_STORE) {
+        const bool full = (int64_t)(blockIdx.y + 1) * kTM <= n && (n & 3) == 0;
+        if (full) {
+            // through LDS, per column tile: the wave's 64 x 32 block is
+            // written column-major (stride kStg floats), then read back as 16
+            // lanes x 16 bytes per column, so each store instruction covers
+            // four whole 256-byte column segments
+            float *stg = L.stg + wave * 32 * kStg;
+            const int rc = lane >> 4, rr = (lane & 15) * 4;
+#pragma unroll
+            for (int ct = 0; ct < 4; ++ct) {
+                __syncthreads();  // the previous tile's reads (or the K loop) are done
+#pragma unroll
+                for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+                    for (int g = 0; g < 4; ++g) {
+                        const f32x4 v = {acc[rt][ct][4 * g], acc[rt][ct][4 * g + 1],
+                                         acc[rt][ct][4 * g + 2], acc[rt][ct][4 * g + 3]};
+                        *(f32x4 *)(stg + lr * kStg + rt * 32 + g * 8 + lh * 4) = v;
+                    }
+                __syncthreads();
+#pragma unroll
+                for (int it = 0; it < 8; ++it) {
+                    const int c = it * 4 + rc;
+                    const int64_t J = J0 + ct * 32 + c;
+                    const f32x4 v = *(const f32x4 *)(stg + c * kStg + rr);
+                    if (J < ncols) *(f32x4 *)(S + J * n + row0 + rr) = v;
+                }
+            }
+            return;
+        }
         // S[J][i]: lane lr writes rows (r / 4) 8 + 4 lh .. + 3 of column J
 #pragma unroll
         for (int ct = 0; ct < 4; ++ct) {

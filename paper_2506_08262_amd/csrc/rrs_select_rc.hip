@@ -63,11 +63,8 @@ struct alignas(16) RcShared {
     float sval[64];
     uint32_t cidx[kCapW];
     double cval[kCapW];
-    float scale, off;            // bins of the current bracket
     uint32_t kmin, kmax;         // order keys of the column's range
-    uint32_t below, ncand, nlow, beforeA;
-    uint32_t binA, binB;
-    int32_t fast;
+    uint32_t ncand, nlow;
     uint32_t count;
     double resA, resB;
     uint32_t sel_bucket, sel_before, sel_count;
@@ -264,8 +261,7 @@ struct RegSrc {
 
 // Rank r (and r + 1 when pair) among the n candidate values held in LDS:
 // radix select over their order-preserving 64-bit keys, 8 bits per pass.
-__device__ void lds_rank_pair(RcShared &sh, uint32_t nc, uint64_t r, bool pair, double &a,
-                              double &b)
+__device__ __noinline__ void lds_rank_pair(RcShared &sh, uint32_t nc, uint64_t r, bool pair)
 {
     const int tid = threadIdx.x;
     uint64_t prefix = 0, pmask = 0, k = r;
@@ -292,9 +288,12 @@ __device__ void lds_rank_pair(RcShared &sh, uint32_t nc, uint64_t r, bool pair, 
         pmask |= 0xFFull << shift;
         __syncthreads();
     }
-    a = key_value(prefix);
-    b = a;
-    if (!pair) return;
+    const double a = key_value(prefix);
+    if (!pair) {
+        if (tid == 0) sh.resA = sh.resB = a;
+        __syncthreads();
+        return;
+    }
     // the next value: A again if more than r + 1 keys are <= A, else the
     // smallest key above A
     if (tid == 0) {
@@ -312,7 +311,10 @@ __device__ void lds_rank_pair(RcShared &sh, uint32_t nc, uint64_t r, bool pair, 
     if (le) atomicAdd(&sh.count, le);
     if (mn != ~0ull) atomicMin((unsigned long long *)&sh.minkey, (unsigned long long)mn);
     __syncthreads();
-    b = ((uint64_t)sh.count >= r + 2) ? a : key_value(sh.minkey);
+    if (tid == 0) {
+        sh.resA = a;
+        sh.resB = ((uint64_t)sh.count >= r + 2) ? a : key_value(sh.minkey);
+    }
     __syncthreads();
 }
 
@@ -457,10 +459,16 @@ __device__ __forceinline__ bool rc_select(const Col &C, const SRC &src, double m
     const int64_t n = C.n;
     const float sigf = (float)sig;
     bool fast = C.sane;
+    float scale = 1.0f, off = 0.0f;
+    int fast0 = 0;
     if (fast) {
         sh.hist[tid] = 0;
         if (tid < kHistN - kT) sh.hist[kT + tid] = 0;
         if (tid < 64) sh.srank[tid] = 0;
+        if (tid == 0) {
+            sh.ncand = 0;
+            sh.nlow = 0;
+        }
         // 64 sampled approximations: slot 16 w + l from lane l < 16 of wave w
         if (lane < 16) {
             const int slot = wave * 16 + lane;
@@ -482,13 +490,13 @@ __device__ __forceinline__ bool rc_select(const Col &C, const SRC &src, double m
             atomicAdd(&sh.srank[lane], part);
         }
         __syncthreads();
-        if (tid < 64) {
+        {
+            // every wave derives the bracket itself (same values, no barrier)
             const uint32_t kx = sh.skey[lane];
             const bool ok = kx != 0xFFFFFFFFu;
             const uint32_t rank = sh.srank[lane];
             const uint32_t S = (uint32_t)__popcll(__ballot(ok));
-            const int fast0 = S >= 16 ? 1 : 0;
-            float scale = 1.0f, off = 0.0f;
+            fast0 = S >= 16 ? 1 : 0;
             if (fast0) {
                 const double f = ((double)k + 0.5) / (double)n;
                 const double pos = f * (double)S;
@@ -503,21 +511,15 @@ __device__ __forceinline__ bool rc_select(const Col &C, const SRC &src, double m
                 const float H = lane_bcast_f(xv, __ffsll((long long)mhi) - 1);
                 lin_fit(L, H, scale, off);
             }
-            if (lane == 0) {
-                sh.scale = scale;
-                sh.off = off;
-                sh.fast = fast0;
-            }
         }
-        __syncthreads();
         // register-resident columns keep a single pass (a miss falls back);
         // streamed columns rebracket and narrow instead
-        fast = SRC::kMaxLevel > 0 || sh.fast != 0;
+        fast = SRC::kMaxLevel > 0 || fast0 != 0;
     }
     if (fast) {
-        float scale = sh.scale, off = sh.off;
         bool whole = false;
-        if (SRC::kMaxLevel > 0 && sh.fast == 0) {
+        uint32_t bA = 0, bB = 0, beforeA = 0;
+        if (SRC::kMaxLevel > 0 && fast0 == 0) {
             // too few samples took part: bracket the whole column
             float L, H;
             fast = rc_range<PH>(src, sigf, sh, L, H);
@@ -536,23 +538,24 @@ __device__ __forceinline__ bool rc_select(const Col &C, const SRC &src, double m
                 atomicAdd(&bins[t], 1u);
             });
             __syncthreads();
-            if (tid < 64) {
+            {
+                // every wave scans the histogram itself (same results)
                 uint32_t lo = sh.hist[lane];  // the below slots
                 for (int o = 32; o > 0; o >>= 1) lo += (uint32_t)__shfl_xor((int)lo, o);
-                uint32_t bA, rA, cA, bB, rB, cB;
+                uint32_t xA, rA, cA, xB, rB, cB;
                 bool fA, fB;
-                scan_hist(bins, lo, k, bA, rA, cA, fA);
-                scan_hist(bins, lo, k + 1, bB, rB, cB, fB);
-                if (fA) {
-                    sh.binA = bA;
-                    sh.beforeA = (uint32_t)(k - rA);
-                }
-                if (fB) sh.binB = bB;
+                scan_hist(bins, lo, k, xA, rA, cA, fA);
+                scan_hist(bins, lo, k + 1, xB, rB, cB, fB);
                 const uint64_t ma = __ballot(fA), mb = __ballot(fB);
-                if (lane == 0) sh.fast = (ma != 0 && (!pair || mb != 0)) ? 1 : 0;
+                fast = ma != 0 && (!pair || mb != 0);
+                if (fast) {
+                    const int la = __ffsll((long long)ma) - 1;
+                    bA = (uint32_t)__builtin_amdgcn_readlane((int)xA, la);
+                    beforeA = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(k - rA), la);
+                    bB = pair ? (uint32_t)__builtin_amdgcn_readlane((int)xB, __ffsll((long long)mb) - 1)
+                              : bA;
+                }
             }
-            __syncthreads();
-            fast = sh.fast != 0;
             if (level >= SRC::kMaxLevel) break;
             float L, H;
             bool rebracket = false;
@@ -564,7 +567,6 @@ __device__ __forceinline__ bool rc_select(const Col &C, const SRC &src, double m
                 if (!fast) break;
                 whole = rebracket = true;
             } else {
-                const uint32_t bA = sh.binA, bB = pair ? sh.binB : sh.binA;
                 uint32_t held = 0;
                 for (uint32_t x = bA; x <= bB; ++x) held += bins[x];
                 if (held <= (uint32_t)kCapW / 2) break;
@@ -583,7 +585,6 @@ __device__ __forceinline__ bool rc_select(const Col &C, const SRC &src, double m
             __syncthreads();
         }
         if (fast) {
-            const uint32_t bA = sh.binA, bB = pair ? sh.binB : sh.binA;
             // approximations of the target bins lie in [vlo, vhi]
             const double vlo = lin_lo(bA, scale, off), vhi = lin_hi(bB, scale, off);
             // phase 1 adds the roundings of sig to binary32 and of s - sig
@@ -598,57 +599,69 @@ __device__ __forceinline__ bool rc_select(const Col &C, const SRC &src, double m
             const float hwf =
                 __double2float_ru((hw + fabs(mid - (double)midf)) * (1.0 + 0x1p-50));
             const float fA = (float)bA;
-            if (tid == 0) {
-                sh.ncand = 0;
-                sh.nlow = 0;
-            }
-            __syncthreads();
             src.each([&](int i, float sv) {
                 const float x = approx_v<PH>(sv, sigf);
                 if (fabsf(x - midf) <= hwf) {
-                    // flag the candidates binned below bin A (t < bA is the
-                    // histogram pass's test, the same fma)
-                    const uint32_t low = fmaf(x, scale, off) < fA ? 0x80000000u : 0u;
+                    // candidates binned below bin A (t < bA is the histogram
+                    // pass's test, the same fma) are counted apart
+                    const bool low = fmaf(x, scale, off) < fA;
+                    if (low) atomicAdd(&sh.nlow, 1u);
                     const uint32_t p = atomicAdd(&sh.ncand, 1u);
-                    if (p < (uint32_t)kCapW) sh.cidx[p] = (uint32_t)i | low;
+                    if (p < (uint32_t)kCapW) sh.cidx[p] = (uint32_t)i;
                 }
             });
             __syncthreads();
             const uint32_t nc = sh.ncand;
-            if (nc <= (uint32_t)kCapW) {
-                uint32_t low = 0;
-                for (uint32_t p = tid; p < nc; p += kT) low += sh.cidx[p] >> 31;
-                for (int o = 32; o > 0; o >>= 1) low += (uint32_t)__shfl_xor((int)low, o);
-                if (lane == 0 && low) atomicAdd(&sh.nlow, low);
-            }
-            __syncthreads();
             // points below the window: those binned below bin A that are not
             // candidates (a non-candidate under bin A lies below wlo)
-            const uint64_t B = (uint64_t)sh.beforeA - sh.nlow;
+            const uint64_t B = (uint64_t)beforeA - sh.nlow;
             fast = nc <= (uint32_t)kCapW && B <= k && k + (pair ? 1 : 0) < B + nc;
             if (fast) {
-                for (uint32_t p = tid; p < nc; p += kT)
-                    sh.cval[p] = exact_v<PH>(
-                        exact_t<EXACT>(C, (int64_t)(sh.cidx[p] & 0x7FFFFFFFu)), med);
+                // the all-pairs ranking counts into cidx[p] (below) and
+                // cidx[kCapW / 2 + p] (at most); each thread clears the slots
+                // of the candidate whose index it has just read
+                const bool quad = nc <= (uint32_t)kQuad;
+                for (uint32_t p = tid; p < nc; p += kT) {
+                    const int64_t i = (int64_t)sh.cidx[p];
+                    if (quad) {
+                        sh.cidx[p] = 0u;
+                        sh.cidx[kCapW / 2 + p] = 0u;
+                    }
+                    sh.cval[p] = exact_v<PH>(exact_t<EXACT>(C, i), med);
+                }
                 __syncthreads();
                 const uint64_t rA = k - B, rB = k + 1 - B;
-                if (nc <= (uint32_t)kQuad) {
-                    for (uint32_t p = tid; p < nc; p += kT) {
+                if (quad) {
+                    // candidate p against a slice of the others, G slices
+                    // per candidate spread over the block
+                    const uint32_t G = nc >= (uint32_t)kT ? 1u : (uint32_t)kT / nc;
+                    const uint32_t span = (nc + G - 1) / G;
+                    for (uint32_t w = tid; w < nc * G; w += kT) {
+                        const uint32_t g = w / nc, p = w - g * nc;
                         const double mine = sh.cval[p];
+                        const uint32_t x0 = g * span, x1 = x0 + span < nc ? x0 + span : nc;
                         uint32_t lt = 0, le = 0;
-                        for (uint32_t x = 0; x < nc; ++x) {
+                        for (uint32_t x = x0; x < x1; ++x) {
                             const double o = sh.cval[x];
                             lt += (o < mine);
                             le += (o <= mine);
                         }
-                        if (lt <= rA && rA < le) sh.resA = mine;
-                        if (pair && lt <= rB && rB < le) sh.resB = mine;
+                        if (lt) atomicAdd(&sh.cidx[p], lt);
+                        if (le) atomicAdd(&sh.cidx[kCapW / 2 + p], le);
+                    }
+                    __syncthreads();
+                    for (uint32_t p = tid; p < nc; p += kT) {
+                        const uint32_t lt = sh.cidx[p], le = sh.cidx[kCapW / 2 + p];
+                        if (lt <= rA && rA < le) sh.resA = sh.cval[p];
+                        if (pair && lt <= rB && rB < le) sh.resB = sh.cval[p];
                     }
                     __syncthreads();
                     a = sh.resA;
                     b = pair ? sh.resB : a;
                 } else {
-                    lds_rank_pair(sh, nc, rA, pair, a, b);
+                    lds_rank_pair(sh, nc, rA, pair);
+                    a = sh.resA;
+                    b = sh.resB;
                 }
                 *below = B;
                 if (stats && tid == 0) atomicAdd(&stats[0], 1u);
