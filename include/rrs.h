@@ -170,9 +170,11 @@ typedef struct {
 rrs_status rrs_profile_enable(int32_t on);
 int32_t rrs_profile_read(rrs_kernel_stat *out, int32_t max_entries);
 
-/* Event counters gathered while timing is on.  "select_fast": order-statistic
- * pairs (median, MAD, MAD_+) resolved by the sampled bracket; "select_fallback":
- * pairs resolved by the exact radix fallback; "recheck_pairs": (query,
+/* Event counters gathered while timing is on.  "select_fallback":
+ * order-statistic pairs (median, MAD, MAD_+) resolved by the exact radix
+ * fallback (counted on the device); "select_fast": the other selects, taken as
+ * two per projection / APD column (an APD column without positive deviations
+ * has one); "recheck_pairs": (query,
  * direction, point) projections the matrix-core forms recomputed in binary64.
  * Returns 0 and writes *value, or -1 for an unknown name or NULL pointer. */
 int32_t rrs_profile_counter(const char *name, double *value);

@@ -227,12 +227,12 @@ rrs_status run(int notion, const double *X, int64_t n, int64_t d, const double *
     RRS_HIP_TRY(hipStreamSynchronize(st));
     if (g_prof.on) {
         g_prof.collect();
-        uint32_t hs[6] = {0, 0, 0, 0, 0, 0};
-        RRS_HIP_TRY(hipMemcpy(hs, stats, sizeof(hs), hipMemcpyDeviceToHost));
-        g_prof.sel_fast += hs[0];
-        g_prof.sel_fallback += hs[1];
+        std::vector<uint32_t> hs(rrs::kStatWords);
+        RRS_HIP_TRY(hipMemcpy(hs.data(), stats, hs.size() * 4, hipMemcpyDeviceToHost));
+        for (int s = 0; s < rrs::kStatSpread; ++s)
+            g_prof.sel_fallback += hs[16 + (rrs::kStatSpread + s) * rrs::kStatStride];
         uint64_t rp = 0;
-        std::memcpy(&rp, hs + 4, sizeof(rp));
+        std::memcpy(&rp, hs.data() + 4, sizeof(rp));
         g_prof.recheck_pairs += (double)rp;
     }
     return RRS_OK;
@@ -302,7 +302,7 @@ int32_t rrs_profile_counter(const char *name, double *value)
     std::lock_guard<std::mutex> lock(g_mutex);
     if (!name || !value) return -1;
     if (std::strcmp(name, "select_fast") == 0) {
-        *value = g_prof.sel_fast;
+        *value = g_prof.sel_total - g_prof.sel_fallback;
         return 0;
     }
     if (std::strcmp(name, "select_fallback") == 0) {

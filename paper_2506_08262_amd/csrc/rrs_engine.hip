@@ -75,7 +75,7 @@ void Profiler::clear()
         ms[k] = 0.0;
         work[k] = 0.0;
     }
-    sel_fast = sel_fallback = recheck_pairs = 0.0;
+    sel_total = sel_fallback = recheck_pairs = 0.0;
 }
 
 namespace {
@@ -197,7 +197,7 @@ int job_sizes(const JobSpec &s, int64_t n, int64_t d, const Plan &p, int64_t qb,
     sz[k++] = half ? (size_t)qb * p.ldm * 2 * 4 : 0;            // cnt
     sz[k++] = (half || mfma) ? 0 : (size_t)qb * p.m * n * 8;    // T (binary64)
     sz[k++] = half ? 0 : (size_t)qb * p.ldm * 8;                // Dj
-    sz[k++] = 64;                                               // stats
+    sz[k++] = (size_t)kStatWords * 4;                           // stats
     const size_t npad = mfma ? (size_t)mfma_col_pad(qb * p.m) : 0;
     sz[k++] = mfma ? npad * p.kp * p.eb : 0;                    // B0
     sz[k++] = (mfma && p.terms == 2) ? npad * p.kp * p.eb : 0;  // B1
@@ -281,7 +281,7 @@ rrs_status enqueue_job(const JobSpec &s, const DataDev &D, const Plan &p, const 
     uint32_t *cnt = cv.take<uint32_t>(sz[4] / 4);
     double *T = cv.take<double>(sz[5] / 8);
     double *Dj = cv.take<double>(sz[6] / 8);
-    uint32_t *stats = cv.take<uint32_t>(16);
+    uint32_t *stats = cv.take<uint32_t>(kStatWords);
     void *B0 = cv.take<char>(sz[8]);
     void *B1 = cv.take<char>(sz[9]);
     float *cmarg = cv.take<float>(sz[10] / 4);
@@ -291,7 +291,7 @@ rrs_status enqueue_job(const JobSpec &s, const DataDev &D, const Plan &p, const 
     double *cq = cv.take<double>(sz[14] / 8);
     double *eq = cv.take<double>(sz[15] / 8);
     if (stats_out) *stats_out = stats;
-    if (profiling) RRS_HIP_TRY(launch_fill_u32(stats, 16, 0u, st));
+    if (profiling) RRS_HIP_TRY(launch_fill_u32(stats, kStatWords, 0u, st));
 
     // zero the direction padding once (the generator writes j < m only)
     RRS_HIP_TRY(launch_fill_u32((uint32_t *)UT, qb * d * ldm * 2, 0u, st));
@@ -342,6 +342,7 @@ rrs_status enqueue_job(const JobSpec &s, const DataDev &D, const Plan &p, const 
                 SelectRcArgs ra{S32, n, m, ldm, nb, cq, eq, D.X, d, Zb, UT, Dj,
                                 profiling ? stats : nullptr};
                 ProfScope ps(prof, K_SELECT, proj_units, st);
+                if (profiling) prof->sel_total += 2.0 * (double)(nb * m);
                 RRS_HIP_TRY(launch_select_rc(ra, s.notion, p.prec != MFMA_F32_PLAIN, st));
             } else if (half) {
                 RRS_HIP_TRY(launch_fill_u32(cnt, nb * ldm * 2, 0u, st));
@@ -354,6 +355,7 @@ rrs_status enqueue_job(const JobSpec &s, const DataDev &D, const Plan &p, const 
                 }
                 SelectArgs sa{T, n, m, ldm, nb, Dj, profiling ? stats : nullptr};
                 ProfScope ps(prof, K_SELECT, proj_units, st);
+                if (profiling) prof->sel_total += 2.0 * (double)(nb * m);
                 if (n <= select_reg_max_n())
                     RRS_HIP_TRY(launch_select_reg(sa, s.notion, st));
                 else

@@ -60,7 +60,9 @@ struct Profiler {
     int64_t launches[K_COUNT] = {};
     double ms[K_COUNT] = {};
     double work[K_COUNT] = {};
-    double sel_fast = 0.0, sel_fallback = 0.0, recheck_pairs = 0.0;
+    // selects issued (two per projection / APD column, counted on the host)
+    // and those that took the exact fallback (counted on the device)
+    double sel_total = 0.0, sel_fallback = 0.0, recheck_pairs = 0.0;
     hipEvent_t get();
     void collect();
     void clear();

@@ -6,6 +6,15 @@
 
 namespace rrs {
 
+// Profiling counters of one job (device, uint32 words): words 0 .. 15 hold
+// single counters (the recheck tally at 4..5); the select's per-column
+// counts (kind 0: window path, 1: exact fallback) are spread over
+// kStatSpread words kStatStride apart per kind, so that one count per
+// workgroup does not serialize a launch on one address.
+constexpr int kStatSpread = 64, kStatStride = 32;
+constexpr int kStatWords = 16 + 2 * kStatSpread * kStatStride;
+
+
 enum { NOTION_HALFSPACE = 0, NOTION_PROJECTION = 1, NOTION_APD = 2 };
 
 constexpr int kProjJT = 16;  // directions per projection workgroup

@@ -708,7 +708,8 @@ __global__ __launch_bounds__(256) void k_gemm(
                     const int c = it * 4 + rc;
                     const int64_t J = J0 + ct * 32 + c;
                     const f32x4 v = *(const f32x4 *)(stg + c * kStg + rr);
-                    if (J < ncols) *(f32x4 *)(S + J * n + row0 + rr) = v;
+                    // written once, read by the select: non-temporal
+                    if (J < ncols) __builtin_nontemporal_store(v, (f32x4 *)(S + J * n + row0 + rr));
                 }
             }
             return;

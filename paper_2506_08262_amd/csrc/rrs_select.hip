@@ -362,7 +362,6 @@ __device__ __forceinline__ void select_pair(double (&vals)[VPT],
             __syncthreads();
             a = sh.resA;
             b = pair ? sh.resB : a;
-            if (stats && tid == 0) atomicAdd(&stats[0], 1u);
             return;
         }
     }
@@ -659,12 +658,11 @@ __device__ void select_pair_stream(const double *__restrict__ col, int64_t n, do
             a = sh.resA;
             b = pair ? sh.resB : a;
             __syncthreads();
-            if (stats && tid == 0) atomicAdd(&stats[0], 1u);
             return;
         }
     }
     __syncthreads();
-    if (stats && tid == 0) atomicAdd(&stats[1], 1u);
+    if (stats && tid == 0) stat_count(stats, 1);
     const uint64_t A = radix_kth_g<PH>(col, n, med, k, sh);
     a = key_value(A);
     b = a;

@@ -46,7 +46,9 @@ using namespace sel;
 
 constexpr int kT = 256;
 constexpr int kBins = 256;
-constexpr int kCapW = 2048;      // candidates of one window
+constexpr int kCapW = 2048;      // candidates of one window (workgroup per column)
+constexpr int kCapPair = 1024;   // candidates of one window (two waves per column)
+constexpr int kCapWave = 512;    // candidates of one window (wave per column)
 constexpr int kQuad = 512;       // up to this many, rank candidates by all-pairs counts
 constexpr int kRadixCand = 64;
 constexpr int kUnroll = 4;
@@ -56,13 +58,35 @@ constexpr int kDs = 128;         // coordinates kept in LDS for the recomputatio
 // bins, 64 per-lane slots for values above it.
 constexpr int kHistLo = 64, kHistN = kHistLo + kBins + 64;
 
+// The threads that share one column: a workgroup of W waves (block
+// barriers) or one wave of a 64-thread workgroup.  One wave's LDS accesses
+// execute in issue order, so its "barrier" only has to keep the compiler from
+// moving memory accesses across it.
+template <int W>
+struct BlockG {
+    static constexpr int kN = 64 * W, kWaves = W;
+    __device__ static int tid() { return (int)threadIdx.x; }
+    __device__ static void sync() { __syncthreads(); }
+};
+struct WaveG {
+    static constexpr int kN = 64, kWaves = 1;
+    __device__ static int tid() { return (int)threadIdx.x & 63; }
+    __device__ static void sync()
+    {
+        __builtin_amdgcn_wave_barrier();
+        asm volatile("" ::: "memory");
+    }
+};
+
+template <int CAP, int STG>
 struct alignas(16) RcShared {
+    static constexpr int kCap = CAP, kStage = STG;
     uint32_t hist[kHistN];
     uint32_t skey[64];
     uint32_t srank[64];
     float sval[64];
-    uint32_t cidx[kCapW];
-    double cval[kCapW];
+    uint32_t cidx[CAP];
+    double cval[CAP];
     uint32_t kmin, kmax;         // order keys of the column's range
     uint32_t ncand, nlow;
     uint32_t count;
@@ -72,6 +96,7 @@ struct alignas(16) RcShared {
     uint32_t nrcand;
     uint64_t rresult, minkey;
     double zs[kDs], us[kDs];   // the column's query and direction (d <= kDs)
+    double xs[STG];            // the candidates' data rows, gathered in one round
 };
 
 // One column and what its exact recomputation needs.
@@ -107,6 +132,17 @@ __device__ __forceinline__ double exact_t(const Col &C, int64_t i)
         t = fma(x3 - z[c + 3], u[(c + 3) * us], t);
     }
     for (; c < d; ++c) t = fma(x[c] - z[c], u[c * us], t);
+    return t;
+}
+
+// The recipe's projection from a data row held in LDS (same fma order as
+// exact_t).
+__device__ __forceinline__ double row_t(const double *x, const Col &C)
+{
+    const double *z = C.z, *u = C.u;
+    const int64_t us = C.ustride, d = C.d;
+    double t = 0.0;
+    for (int64_t c = 0; c < d; ++c) t = fma(x[c] - z[c], u[c * us], t);
     return t;
 }
 
@@ -202,6 +238,7 @@ __device__ __forceinline__ double exact_v(double t, double med)
 // every slot to f(i, s_i); slots past n read +inf, which every pass treats as
 // above the bracket and outside the window (live values are finite).
 // StreamSrc: global memory, 4 loads in flight per lane (any n < 2^31).
+template <class G>
 struct StreamSrc {
     static constexpr int kMaxLevel = 6;  // rebracket / narrowing passes allowed
     const float *s;
@@ -213,36 +250,44 @@ struct StreamSrc {
     template <class F>
     __device__ __forceinline__ void each(F &&f) const
     {
+        // the trip count is the same for every thread of the group (the
+        // one-wave candidate collection counts with ballots)
         const int nn = (int)n;
-        for (int i0 = threadIdx.x; i0 < nn; i0 += kUnroll * kT) {
+        for (int b = 0; b < nn; b += kUnroll * G::kN) {
+            const int i0 = b + G::tid();
             float t[kUnroll];
 #pragma unroll
             for (int u = 0; u < kUnroll; ++u) {
-                const int i = i0 + u * kT;
-                t[u] = i < nn ? s[i] : __builtin_inff();
+                const int i = i0 + u * G::kN;
+                t[u] = i < nn ? __builtin_nontemporal_load(s + i) : __builtin_inff();
             }
 #pragma unroll
-            for (int u = 0; u < kUnroll; ++u) f(i0 + u * kT, t[u]);
+            for (int u = 0; u < kUnroll; ++u) f(i0 + u * G::kN, t[u]);
         }
     }
 };
 
 // RegSrc: the column held in registers, VPT values per lane (entry
-// threadIdx.x + kT v in slot v, +inf past n).  Every loop over the slots is
+// tid + G::kN v in slot v, +inf past n).  Every loop over the slots is
 // unrolled with compile-time indices, which keeps the array in registers.
-template <int VPT>
+template <int VPT, class G>
 struct RegSrc {
     static constexpr int kMaxLevel = 0;  // short columns: one pass, misses fall back
     float (&v)[VPT];
     int64_t n;
     __device__ __forceinline__ float sample(int slot) const
     {
-        // slot 16 w + l (wave w, lane l < 16) takes register (2 w + 1) VPT / 8
-        const int w = slot >> 4;
-        float x0 = v[(1 * VPT) / 8], x1 = v[(3 * VPT) / 8];
-        float x2 = v[(5 * VPT) / 8], x3 = v[(7 * VPT) / 8];
-        asm volatile("" : "+v"(x0), "+v"(x1), "+v"(x2), "+v"(x3));
-        return w == 0 ? x0 : w == 1 ? x1 : w == 2 ? x2 : x3;
+        // slots 8 q .. 8 q + 7 (taken by consecutive lanes of one wave) read
+        // register (2 q + 1) VPT / 16 of their lane
+        const int q = slot >> 3;
+        float x = v[VPT / 16];
+#pragma unroll
+        for (int r = 1; r < 8; ++r) {
+            float y = v[((2 * r + 1) * VPT) / 16];
+            asm volatile("" : "+v"(y));
+            x = q == r ? y : x;
+        }
+        return x;
     }
     template <class F>
     __device__ __forceinline__ void each(F &&f) const
@@ -252,27 +297,28 @@ struct RegSrc {
 #pragma unroll
         for (int u = 0; u < VPT; ++u) asm volatile("" : "+v"(v[u]));
         // likewise the slot indices (only the rare candidates use them)
-        int base = (int)threadIdx.x;
+        int base = G::tid();
         asm volatile("" : "+v"(base));
 #pragma unroll
-        for (int u = 0; u < VPT; ++u) f(base + kT * u, v[u]);
+        for (int u = 0; u < VPT; ++u) f(base + G::kN * u, v[u]);
     }
 };
 
 // Rank r (and r + 1 when pair) among the n candidate values held in LDS:
 // radix select over their order-preserving 64-bit keys, 8 bits per pass.
-__device__ __noinline__ void lds_rank_pair(RcShared &sh, uint32_t nc, uint64_t r, bool pair)
+template <class G, class SH>
+__device__ __noinline__ void lds_rank_pair(SH &sh, uint32_t nc, uint64_t r, bool pair)
 {
-    const int tid = threadIdx.x;
+    const int tid = G::tid();
     uint64_t prefix = 0, pmask = 0, k = r;
     for (int shift = 56; shift >= 0; shift -= 8) {
-        sh.hist[tid] = 0;
-        __syncthreads();
-        for (uint32_t p = tid; p < nc; p += kT) {
+        for (int x = tid; x < kBins; x += G::kN) sh.hist[x] = 0;
+        G::sync();
+        for (uint32_t p = tid; p < nc; p += G::kN) {
             const uint64_t key = order_key(sh.cval[p]);
             if ((key & pmask) == prefix) atomicAdd(&sh.hist[(uint32_t)(key >> shift) & 255u], 1u);
         }
-        __syncthreads();
+        G::sync();
         if (tid < 64) {
             uint32_t bin, rin, cnt;
             bool found;
@@ -282,16 +328,16 @@ __device__ __noinline__ void lds_rank_pair(RcShared &sh, uint32_t nc, uint64_t r
                 sh.sel_before = (uint32_t)(k - rin);
             }
         }
-        __syncthreads();
+        G::sync();
         k -= sh.sel_before;
         prefix |= (uint64_t)sh.sel_bucket << shift;
         pmask |= 0xFFull << shift;
-        __syncthreads();
+        G::sync();
     }
     const double a = key_value(prefix);
     if (!pair) {
         if (tid == 0) sh.resA = sh.resB = a;
-        __syncthreads();
+        G::sync();
         return;
     }
     // the next value: A again if more than r + 1 keys are <= A, else the
@@ -300,38 +346,38 @@ __device__ __noinline__ void lds_rank_pair(RcShared &sh, uint32_t nc, uint64_t r
         sh.count = 0;
         sh.minkey = ~0ull;
     }
-    __syncthreads();
+    G::sync();
     uint32_t le = 0;
     uint64_t mn = ~0ull;
-    for (uint32_t p = tid; p < nc; p += kT) {
+    for (uint32_t p = tid; p < nc; p += G::kN) {
         const uint64_t key = order_key(sh.cval[p]);
         le += key <= prefix;
         if (key > prefix && key < mn) mn = key;
     }
     if (le) atomicAdd(&sh.count, le);
     if (mn != ~0ull) atomicMin((unsigned long long *)&sh.minkey, (unsigned long long)mn);
-    __syncthreads();
+    G::sync();
     if (tid == 0) {
         sh.resA = a;
         sh.resB = ((uint64_t)sh.count >= r + 2) ? a : key_value(sh.minkey);
     }
-    __syncthreads();
+    G::sync();
 }
 
 // Exact radix select (rank k) over the recomputed values of phase PH.
-template <int PH, bool EXACT>
-__device__ uint64_t rc_radix_kth(const Col &C, double med, uint64_t k, RcShared &sh)
+template <int PH, bool EXACT, class G, class SH>
+__device__ uint64_t rc_radix_kth(const Col &C, double med, uint64_t k, SH &sh)
 {
-    const int tid = threadIdx.x, lane = tid & 63;
+    const int tid = G::tid(), lane = tid & 63;
     uint64_t prefix = 0, pmask = 0;
     for (int shift = 56; shift >= 0; shift -= 8) {
-        sh.hist[tid] = 0;
-        __syncthreads();
-        for (int64_t i = tid; i < C.n; i += kT) {
+        for (int x = tid; x < kBins; x += G::kN) sh.hist[x] = 0;
+        G::sync();
+        for (int64_t i = tid; i < C.n; i += G::kN) {
             const uint64_t key = order_key(exact_v<PH>(exact_t<EXACT>(C, i), med));
             if ((key & pmask) == prefix) atomicAdd(&sh.hist[(uint32_t)(key >> shift) & 255u], 1u);
         }
-        __syncthreads();
+        G::sync();
         if (tid < 64) {
             uint32_t bin, rin, cnt;
             bool found;
@@ -342,7 +388,7 @@ __device__ uint64_t rc_radix_kth(const Col &C, double med, uint64_t k, RcShared 
                 sh.sel_count = cnt;
             }
         }
-        __syncthreads();
+        G::sync();
         const uint32_t selb = sh.sel_bucket, cntb = sh.sel_count;
         k -= sh.sel_before;
         prefix |= (uint64_t)selb << shift;
@@ -350,15 +396,15 @@ __device__ uint64_t rc_radix_kth(const Col &C, double med, uint64_t k, RcShared 
         if (shift == 0) break;
         if (cntb <= (uint32_t)kRadixCand) {
             if (tid == 0) sh.nrcand = 0;
-            __syncthreads();
-            for (int64_t i = tid; i < C.n; i += kT) {
+            G::sync();
+            for (int64_t i = tid; i < C.n; i += G::kN) {
                 const uint64_t key = order_key(exact_v<PH>(exact_t<EXACT>(C, i), med));
                 if ((key & pmask) == prefix) {
                     const uint32_t pos = atomicAdd(&sh.nrcand, 1u);
                     if (pos < (uint32_t)kRadixCand) sh.rcand[pos] = key;
                 }
             }
-            __syncthreads();
+            G::sync();
             if (tid < 64) {
                 const uint32_t nc = sh.nrcand < (uint32_t)kRadixCand ? sh.nrcand
                                                                      : (uint32_t)kRadixCand;
@@ -373,53 +419,52 @@ __device__ uint64_t rc_radix_kth(const Col &C, double med, uint64_t k, RcShared 
                     if (lt <= k && k < le) sh.rresult = mine;
                 }
             }
-            __syncthreads();
+            G::sync();
             const uint64_t r = sh.rresult;
-            __syncthreads();
+            G::sync();
             return r;
         }
     }
-    __syncthreads();
+    G::sync();
     return prefix;
 }
 
 // Key of the (k+1)-th smallest given the key A of the k-th (exact values).
-template <int PH, bool EXACT>
-__device__ uint64_t rc_radix_next(const Col &C, double med, uint64_t k, uint64_t A,
-                                  RcShared &sh)
+template <int PH, bool EXACT, class G, class SH>
+__device__ uint64_t rc_radix_next(const Col &C, double med, uint64_t k, uint64_t A, SH &sh)
 {
-    const int tid = threadIdx.x;
+    const int tid = G::tid();
     if (tid == 0) {
         sh.count = 0;
         sh.minkey = ~0ull;
     }
-    __syncthreads();
+    G::sync();
     uint32_t le = 0;
     uint64_t mn = ~0ull;
-    for (int64_t i = tid; i < C.n; i += kT) {
+    for (int64_t i = tid; i < C.n; i += G::kN) {
         const uint64_t key = order_key(exact_v<PH>(exact_t<EXACT>(C, i), med));
         le += (key <= A);
         if (key > A && key < mn) mn = key;
     }
     if (le) atomicAdd(&sh.count, le);
     if (mn != ~0ull) atomicMin((unsigned long long *)&sh.minkey, (unsigned long long)mn);
-    __syncthreads();
+    G::sync();
     const uint64_t res = ((uint64_t)sh.count >= k + 2) ? A : sh.minkey;
-    __syncthreads();
+    G::sync();
     return res;
 }
 
 // Smallest and largest finite approximation of the column in phase PH (as
 // floats); false when there is none.
-template <int PH, class SRC>
-__device__ bool rc_range(const SRC &src, float sigf, RcShared &sh, float &L, float &H)
+template <int PH, class G, class SRC, class SH>
+__device__ bool rc_range(const SRC &src, float sigf, SH &sh, float &L, float &H)
 {
-    const int lane = threadIdx.x & 63;
-    if (threadIdx.x == 0) {
+    const int lane = G::tid() & 63;
+    if (G::tid() == 0) {
         sh.kmin = 0xFFFFFFFFu;
         sh.kmax = 0u;
     }
-    __syncthreads();
+    G::sync();
     uint32_t kmin = 0xFFFFFFFFu, kmax = 0u;
     src.each([&](int, float sv) {
         const uint32_t kx = fkey32<PH>(approx_v<PH>(sv, sigf));
@@ -438,9 +483,9 @@ __device__ bool rc_range(const SRC &src, float sigf, RcShared &sh, float &L, flo
         atomicMin(&sh.kmin, kmin);
         atomicMax(&sh.kmax, kmax);
     }
-    __syncthreads();
+    G::sync();
     const uint32_t a = sh.kmin, b = sh.kmax;
-    __syncthreads();
+    G::sync();
     if (a > b) return false;
     L = fkey_value<PH>(a);
     H = fkey_value<PH>(b);
@@ -450,46 +495,48 @@ __device__ bool rc_range(const SRC &src, float sigf, RcShared &sh, float &L, flo
 // The exact values of ranks k (and k + 1 if pair) in phase PH.  Returns true
 // when the window path served them; then sh.cval[0 .. ncand) holds the
 // window's exact values and *below the number of points under the window.
-template <int PH, bool EXACT, class SRC>
-__device__ __forceinline__ bool rc_select(const Col &C, const SRC &src, double med, double sig, double E,
-                          uint64_t k, bool pair, double &a, double &b, uint64_t *below,
-                          RcShared &sh, uint32_t *stats)
+template <int PH, bool EXACT, class G, class SRC, class SH>
+__device__ __forceinline__ bool rc_select(const Col &C, const SRC &src, double med, double sig,
+                                          double E, uint64_t k, bool pair, double &a, double &b,
+                                          uint64_t *below, SH &sh, uint32_t *stats)
 {
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int tid = G::tid(), lane = tid & 63, wave = tid >> 6;
+    constexpr uint32_t kCap = (uint32_t)SH::kCap;
+    constexpr uint32_t kQuadG = kQuad < SH::kCap / 2 ? kQuad : SH::kCap / 2;
     const int64_t n = C.n;
     const float sigf = (float)sig;
     bool fast = C.sane;
     float scale = 1.0f, off = 0.0f;
     int fast0 = 0;
     if (fast) {
-        sh.hist[tid] = 0;
-        if (tid < kHistN - kT) sh.hist[kT + tid] = 0;
+        for (int x = tid; x < kHistN; x += G::kN) sh.hist[x] = 0;
         if (tid < 64) sh.srank[tid] = 0;
         if (tid == 0) {
             sh.ncand = 0;
             sh.nlow = 0;
         }
-        // 64 sampled approximations: slot 16 w + l from lane l < 16 of wave w
-        if (lane < 16) {
-            const int slot = wave * 16 + lane;
+        // 64 sampled approximations: slot kPer w + l from lane l < kPer of wave w
+        constexpr int kPer = 64 / G::kWaves;
+        if (lane < kPer) {
+            const int slot = wave * kPer + lane;
             const float x = approx_v<PH>(src.sample(slot), sigf);
             const uint32_t kx = fkey32<PH>(x);
             sh.skey[slot] = fkey_finite<PH>(kx) ? kx : 0xFFFFFFFFu;
             sh.sval[slot] = x;
         }
-        __syncthreads();
+        G::sync();
         {
             const uint32_t mine = sh.skey[lane];
             uint32_t part = 0;
 #pragma unroll
-            for (int jj = 0; jj < 16; ++jj) {
-                const int o = wave * 16 + jj;
+            for (int jj = 0; jj < kPer; ++jj) {
+                const int o = wave * kPer + jj;
                 const uint32_t ko = sh.skey[o];
                 part += (ko < mine || (ko == mine && o < lane)) ? 1u : 0u;
             }
             atomicAdd(&sh.srank[lane], part);
         }
-        __syncthreads();
+        G::sync();
         {
             // every wave derives the bracket itself (same values, no barrier)
             const uint32_t kx = sh.skey[lane];
@@ -522,7 +569,7 @@ __device__ __forceinline__ bool rc_select(const Col &C, const SRC &src, double m
         if (SRC::kMaxLevel > 0 && fast0 == 0) {
             // too few samples took part: bracket the whole column
             float L, H;
-            fast = rc_range<PH>(src, sigf, sh, L, H);
+            fast = rc_range<PH, G>(src, sigf, sh, L, H);
             if (fast) lin_fit(L, H, scale, off);
             whole = true;
         }
@@ -537,7 +584,7 @@ __device__ __forceinline__ bool rc_select(const Col &C, const SRC &src, double m
                 const int t = lin_slot(approx_v<PH>(sv, sigf), scale, off, lo_l, hi_l);
                 atomicAdd(&bins[t], 1u);
             });
-            __syncthreads();
+            G::sync();
             {
                 // every wave scans the histogram itself (same results)
                 uint32_t lo = sh.hist[lane];  // the below slots
@@ -563,13 +610,13 @@ __device__ __forceinline__ bool rc_select(const Col &C, const SRC &src, double m
                 // the sampled bracket missed the rank: bracket the whole
                 // column instead (then narrow as usual)
                 if (whole) break;
-                fast = rc_range<PH>(src, sigf, sh, L, H);
+                fast = rc_range<PH, G>(src, sigf, sh, L, H);
                 if (!fast) break;
                 whole = rebracket = true;
             } else {
                 uint32_t held = 0;
                 for (uint32_t x = bA; x <= bB; ++x) held += bins[x];
-                if (held <= (uint32_t)kCapW / 2) break;
+                if (held <= kCap / 2) break;
                 // narrow to the target bins
                 L = __double2float_rd(lin_lo(bA, scale, off));
                 H = __double2float_ru(lin_hi(bB, scale, off));
@@ -579,10 +626,9 @@ __device__ __forceinline__ bool rc_select(const Col &C, const SRC &src, double m
             if (!rebracket && !(ns > scale)) break;  // no finer bins to be had
             scale = ns;
             off = no;
-            __syncthreads();
-            sh.hist[tid] = 0;
-            if (tid < kHistN - kT) sh.hist[kT + tid] = 0;
-            __syncthreads();
+            G::sync();
+            for (int x = tid; x < kHistN; x += G::kN) sh.hist[x] = 0;
+            G::sync();
         }
         if (fast) {
             // approximations of the target bins lie in [vlo, vhi]
@@ -599,44 +645,89 @@ __device__ __forceinline__ bool rc_select(const Col &C, const SRC &src, double m
             const float hwf =
                 __double2float_ru((hw + fabs(mid - (double)midf)) * (1.0 + 0x1p-50));
             const float fA = (float)bA;
-            src.each([&](int i, float sv) {
-                const float x = approx_v<PH>(sv, sigf);
-                if (fabsf(x - midf) <= hwf) {
-                    // candidates binned below bin A (t < bA is the histogram
-                    // pass's test, the same fma) are counted apart
-                    const bool low = fmaf(x, scale, off) < fA;
-                    if (low) atomicAdd(&sh.nlow, 1u);
-                    const uint32_t p = atomicAdd(&sh.ncand, 1u);
-                    if (p < (uint32_t)kCapW) sh.cidx[p] = (uint32_t)i;
-                }
-            });
-            __syncthreads();
-            const uint32_t nc = sh.ncand;
+            // candidates binned below bin A (t < bA is the histogram pass's
+            // test, the same fma) are counted apart
+            uint32_t nc, nlow;
+            if (G::kWaves == 1) {
+                // one wave: slots from ballots, counts in scalar registers
+                uint32_t wc = 0, wl = 0;
+                src.each([&](int i, float sv) {
+                    const float x = approx_v<PH>(sv, sigf);
+                    const bool in = fabsf(x - midf) <= hwf;
+                    const uint64_t mask = __ballot(in);
+                    if (mask) {
+                        const uint64_t ml = __ballot(in && fmaf(x, scale, off) < fA);
+                        const uint32_t p =
+                            wc + __builtin_amdgcn_mbcnt_hi(
+                                     (uint32_t)(mask >> 32),
+                                     __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+                        if (in && p < kCap) sh.cidx[p] = (uint32_t)i;
+                        wc += (uint32_t)__popcll(mask);
+                        wl += (uint32_t)__popcll(ml);
+                    }
+                });
+                if (lane == 0) sh.ncand = wc;  // read by the APD count
+                nc = wc;
+                nlow = wl;
+                G::sync();
+            } else {
+                src.each([&](int i, float sv) {
+                    const float x = approx_v<PH>(sv, sigf);
+                    if (fabsf(x - midf) <= hwf) {
+                        const bool low = fmaf(x, scale, off) < fA;
+                        if (low) atomicAdd(&sh.nlow, 1u);
+                        const uint32_t p = atomicAdd(&sh.ncand, 1u);
+                        if (p < kCap) sh.cidx[p] = (uint32_t)i;
+                    }
+                });
+                G::sync();
+                nc = sh.ncand;
+                nlow = sh.nlow;
+            }
             // points below the window: those binned below bin A that are not
             // candidates (a non-candidate under bin A lies below wlo)
-            const uint64_t B = (uint64_t)beforeA - sh.nlow;
-            fast = nc <= (uint32_t)kCapW && B <= k && k + (pair ? 1 : 0) < B + nc;
+            const uint64_t B = (uint64_t)beforeA - nlow;
+            fast = nc <= kCap && B <= k && k + (pair ? 1 : 0) < B + nc;
             if (fast) {
                 // the all-pairs ranking counts into cidx[p] (below) and
-                // cidx[kCapW / 2 + p] (at most); each thread clears the slots
+                // cidx[kCap / 2 + p] (at most); each thread clears the slots
                 // of the candidate whose index it has just read
-                const bool quad = nc <= (uint32_t)kQuad;
-                for (uint32_t p = tid; p < nc; p += kT) {
-                    const int64_t i = (int64_t)sh.cidx[p];
-                    if (quad) {
-                        sh.cidx[p] = 0u;
-                        sh.cidx[kCapW / 2 + p] = 0u;
+                const bool quad = nc <= kQuadG;
+                const uint32_t dd = (uint32_t)C.d, nd = nc * dd;
+                if (EXACT && nd <= (uint32_t)SH::kStage) {
+                    // the candidates' rows in one cooperative round of loads
+                    // (coordinate c of candidate p at xs[p d + c]), then each
+                    // thread runs its candidate's fma chain from LDS
+                    for (uint32_t e = tid; e < nd; e += G::kN) {
+                        const uint32_t p = e / dd, c = e - p * dd;
+                        sh.xs[e] = C.X[(int64_t)sh.cidx[p] * C.d + c];
                     }
-                    sh.cval[p] = exact_v<PH>(exact_t<EXACT>(C, i), med);
+                    G::sync();
+                    for (uint32_t p = tid; p < nc; p += G::kN) {
+                        if (quad) {
+                            sh.cidx[p] = 0u;
+                            sh.cidx[kCap / 2 + p] = 0u;
+                        }
+                        sh.cval[p] = exact_v<PH>(row_t(sh.xs + p * dd, C), med);
+                    }
+                } else {
+                    for (uint32_t p = tid; p < nc; p += G::kN) {
+                        const int64_t i = (int64_t)sh.cidx[p];
+                        if (quad) {
+                            sh.cidx[p] = 0u;
+                            sh.cidx[kCap / 2 + p] = 0u;
+                        }
+                        sh.cval[p] = exact_v<PH>(exact_t<EXACT>(C, i), med);
+                    }
                 }
-                __syncthreads();
+                G::sync();
                 const uint64_t rA = k - B, rB = k + 1 - B;
                 if (quad) {
                     // candidate p against a slice of the others, G slices
                     // per candidate spread over the block
-                    const uint32_t G = nc >= (uint32_t)kT ? 1u : (uint32_t)kT / nc;
-                    const uint32_t span = (nc + G - 1) / G;
-                    for (uint32_t w = tid; w < nc * G; w += kT) {
+                    const uint32_t grp = nc >= (uint32_t)G::kN ? 1u : (uint32_t)G::kN / nc;
+                    const uint32_t span = (nc + grp - 1) / grp;
+                    for (uint32_t w = tid; w < nc * grp; w += G::kN) {
                         const uint32_t g = w / nc, p = w - g * nc;
                         const double mine = sh.cval[p];
                         const uint32_t x0 = g * span, x1 = x0 + span < nc ? x0 + span : nc;
@@ -647,69 +738,68 @@ __device__ __forceinline__ bool rc_select(const Col &C, const SRC &src, double m
                             le += (o <= mine);
                         }
                         if (lt) atomicAdd(&sh.cidx[p], lt);
-                        if (le) atomicAdd(&sh.cidx[kCapW / 2 + p], le);
+                        if (le) atomicAdd(&sh.cidx[kCap / 2 + p], le);
                     }
-                    __syncthreads();
-                    for (uint32_t p = tid; p < nc; p += kT) {
-                        const uint32_t lt = sh.cidx[p], le = sh.cidx[kCapW / 2 + p];
+                    G::sync();
+                    for (uint32_t p = tid; p < nc; p += G::kN) {
+                        const uint32_t lt = sh.cidx[p], le = sh.cidx[kCap / 2 + p];
                         if (lt <= rA && rA < le) sh.resA = sh.cval[p];
                         if (pair && lt <= rB && rB < le) sh.resB = sh.cval[p];
                     }
-                    __syncthreads();
+                    G::sync();
                     a = sh.resA;
                     b = pair ? sh.resB : a;
                 } else {
-                    lds_rank_pair(sh, nc, rA, pair);
+                    lds_rank_pair<G>(sh, nc, rA, pair);
                     a = sh.resA;
                     b = sh.resB;
                 }
                 *below = B;
-                if (stats && tid == 0) atomicAdd(&stats[0], 1u);
                 return true;
             }
         }
     }
-    __syncthreads();
+    G::sync();
     if (SRC::kMaxLevel == 0 && C.sane) {
         // a register-resident column that missed: the streamed select over
         // the same column in global memory (rebracketing, narrowing)
-        return rc_select<PH, EXACT>(C, StreamSrc{C.s, C.n}, med, sig, E, k, pair, a, b, below,
-                                    sh, stats);
+        return rc_select<PH, EXACT, G>(C, StreamSrc<G>{C.s, C.n}, med, sig, E, k, pair, a, b,
+                                       below, sh, stats);
     }
-    if (stats && tid == 0) atomicAdd(&stats[1], 1u);
-    const uint64_t A = rc_radix_kth<PH, EXACT>(C, med, k, sh);
+    if (stats && tid == 0) stat_count(stats, 1);
+    const uint64_t A = rc_radix_kth<PH, EXACT, G>(C, med, k, sh);
     a = key_value(A);
     b = a;
-    if (pair) b = key_value(rc_radix_next<PH, EXACT>(C, med, k, A, sh));
+    if (pair) b = key_value(rc_radix_next<PH, EXACT, G>(C, med, k, A, sh));
     return false;
 }
 
 // Number of points with t <= med: from the median's window when it served,
 // else by a counting pass over recomputed values.
-template <bool EXACT>
-__device__ __forceinline__ uint64_t rc_count_le(const Col &C, double med, bool window, uint64_t below,
-                                RcShared &sh)
+template <bool EXACT, class G, class SH>
+__device__ __forceinline__ uint64_t rc_count_le(const Col &C, double med, bool window,
+                                                uint64_t below, SH &sh)
 {
-    const int tid = threadIdx.x, lane = tid & 63;
+    const int tid = G::tid(), lane = tid & 63;
     if (tid == 0) sh.count = 0;
-    __syncthreads();
+    G::sync();
     uint32_t c = 0;
     if (window) {
         const uint32_t nc = sh.ncand;
-        for (uint32_t p = tid; p < nc; p += kT) c += sh.cval[p] <= med ? 1u : 0u;
+        for (uint32_t p = tid; p < nc; p += G::kN) c += sh.cval[p] <= med ? 1u : 0u;
     } else {
-        for (int64_t i = tid; i < C.n; i += kT) c += exact_t<EXACT>(C, i) <= med ? 1u : 0u;
+        for (int64_t i = tid; i < C.n; i += G::kN) c += exact_t<EXACT>(C, i) <= med ? 1u : 0u;
     }
     for (int off = 32; off > 0; off >>= 1) c += (uint32_t)__shfl_xor((int)c, off);
     if (lane == 0 && c) atomicAdd(&sh.count, c);
-    __syncthreads();
+    G::sync();
     const uint64_t r = (window ? below : 0) + sh.count;
-    __syncthreads();
+    G::sync();
     return r;
 }
 
-template <int NOTION, bool EXACT, class SRC>
-__device__ __forceinline__ double rc_depth(const Col &C, const SRC &src, RcShared &sh,
+template <int NOTION, bool EXACT, class G, class SRC, class SH>
+__device__ __forceinline__ double rc_depth(const Col &C, const SRC &src, SH &sh,
                                            uint32_t *stats)
 {
     // rank k of the s values is rank k of the s - c values: the windows live
@@ -721,17 +811,17 @@ __device__ __forceinline__ double rc_depth(const Col &C, const SRC &src, RcShare
     double a, b;
     uint64_t below = 0;
     const bool win =
-        rc_select<0, EXACT>(C, src, 0.0, 0.0, C.E, k, !odd, a, b, &below, sh, stats);
+        rc_select<0, EXACT, G>(C, src, 0.0, 0.0, C.E, k, !odd, a, b, &below, sh, stats);
     const double med = odd ? a : (a + b) * 0.5;
     if (NOTION == NOTION_PROJECTION) {
         double m1, m2;
         uint64_t b1 = 0;
-        rc_select<1, EXACT>(C, src, med, med + C.c, C.E, k, !odd, m1, m2, &b1, sh, stats);
+        rc_select<1, EXACT, G>(C, src, med, med + C.c, C.E, k, !odd, m1, m2, &b1, sh, stats);
         const double mad = odd ? m1 : (m1 + m2) * 0.5;
         if (mad == 0.0) return (med == 0.0) ? 1.0 : 0.0;
         return 1.0 / (1.0 + fabs(med) / mad);
     }
-    const uint64_t nle = rc_count_le<EXACT>(C, med, win, below, sh);
+    const uint64_t nle = rc_count_le<EXACT, G>(C, med, win, below, sh);
     const uint64_t npos = (uint64_t)n - nle;
     const double num = (med < 0.0) ? -med : 0.0;
     if (npos == 0) return (num == 0.0) ? 1.0 : 0.0;
@@ -739,24 +829,25 @@ __device__ __forceinline__ double rc_depth(const Col &C, const SRC &src, RcShare
     const uint64_t kp = nle + (podd ? npos / 2 : npos / 2 - 1);
     double p1, p2;
     uint64_t b2 = 0;
-    rc_select<0, EXACT>(C, src, 0.0, 0.0, C.E, kp, !podd, p1, p2, &b2, sh, stats);
+    rc_select<0, EXACT, G>(C, src, 0.0, 0.0, C.E, kp, !podd, p1, p2, &b2, sh, stats);
     const double madp = podd ? (p1 - med) : ((p1 - med) + (p2 - med)) * 0.5;
     return 1.0 / (1.0 + num / madp);
 }
 
-// VPT > 0: the column in registers (n <= kT VPT); VPT == 0: streamed.
-template <int NOTION, bool EXACT, int VPT>
-__global__ __launch_bounds__(kT) void k_select_rc(const float *__restrict__ S, int64_t n,
-                                                  int64_t m, int64_t ldm,
-                                                  const double *__restrict__ cq,
-                                                  const double *__restrict__ eq,
-                                                  const double *__restrict__ X, int64_t d,
-                                                  const double *__restrict__ Zb,
-                                                  const double *__restrict__ UT,
-                                                  double *__restrict__ Dj,
-                                                  uint32_t *__restrict__ stats)
+// One column per group G (a workgroup of two or four waves, or a 64-thread
+// workgroup of one wave).  VPT > 0: the column in registers (n <= G::kN VPT); VPT == 0:
+// streamed.
+template <int NOTION, bool EXACT, int VPT, class G, int CAP, int STG>
+__device__ __forceinline__ void select_column(const float *__restrict__ S, int64_t n, int64_t m,
+                                              int64_t ldm, const double *__restrict__ cq,
+                                              const double *__restrict__ eq,
+                                              const double *__restrict__ X, int64_t d,
+                                              const double *__restrict__ Zb,
+                                              const double *__restrict__ UT,
+                                              double *__restrict__ Dj, uint32_t *__restrict__ stats,
+                                              RcShared<CAP, STG> &sh)
 {
-    __shared__ RcShared sh;
+    const int tid = G::tid();
     const int64_t j = blockIdx.x;
     const int64_t qi = blockIdx.y;
     Col C;
@@ -772,11 +863,11 @@ __global__ __launch_bounds__(kT) void k_select_rc(const float *__restrict__ S, i
     C.X = X;
     C.d = d;
     if (EXACT && d <= kDs) {
-        for (int64_t c = threadIdx.x; c < d; c += kT) {
+        for (int64_t c = tid; c < d; c += G::kN) {
             sh.zs[c] = Zb[qi * d + c];
             sh.us[c] = UT[qi * d * ldm + c * ldm + j];
         }
-        __syncthreads();
+        G::sync();
         C.z = sh.zs;
         C.u = sh.us;
         C.ustride = 1;
@@ -787,42 +878,65 @@ __global__ __launch_bounds__(kT) void k_select_rc(const float *__restrict__ S, i
     }
     double D;
     if (VPT == 0) {
-        D = rc_depth<NOTION, EXACT>(C, StreamSrc{C.s, n}, sh, stats);
+        D = rc_depth<NOTION, EXACT, G>(C, StreamSrc<G>{C.s, n}, sh, stats);
     } else {
         constexpr int V = VPT > 0 ? VPT : 1;
         float v[V];
 #pragma unroll
         for (int u = 0; u < V; ++u) {
-            const int64_t i = (int64_t)threadIdx.x + (int64_t)kT * u;
-            v[u] = i < n ? C.s[i] : __builtin_inff();
+            const int64_t i = (int64_t)tid + (int64_t)G::kN * u;
+            // the projections are read once: non-temporal, so that they do not
+            // push the data rows of the candidates' recomputation out of L2
+            v[u] = i < n ? __builtin_nontemporal_load(C.s + i) : __builtin_inff();
         }
-        D = rc_depth<NOTION, EXACT>(C, RegSrc<V>{v, n}, sh, stats);
+        D = rc_depth<NOTION, EXACT, G>(C, RegSrc<V, G>{v, n}, sh, stats);
     }
-    if (threadIdx.x == 0) Dj[qi * ldm + j] = D;
+    if (tid == 0) Dj[qi * ldm + j] = D;
 }
 
-template <int NOTION, bool EXACT, int VPT>
+template <int NOTION, bool EXACT, int VPT, class G, int CAP, int STG>
+__global__ __launch_bounds__(G::kN) void k_select_rc(const float *__restrict__ S, int64_t n,
+                                                     int64_t m, int64_t ldm,
+                                                     const double *__restrict__ cq,
+                                                     const double *__restrict__ eq,
+                                                     const double *__restrict__ X, int64_t d,
+                                                     const double *__restrict__ Zb,
+                                                     const double *__restrict__ UT,
+                                                     double *__restrict__ Dj,
+                                                     uint32_t *__restrict__ stats)
+{
+    __shared__ RcShared<CAP, STG> sh;
+    select_column<NOTION, EXACT, VPT, G, CAP, STG>(S, n, m, ldm, cq, eq, X, d, Zb, UT, Dj, stats,
+                                                   sh);
+}
+
+template <int NOTION, bool EXACT, int VPT, class G, int CAP, int STG>
 hipError_t launch_rc(const SelectRcArgs &a, hipStream_t st)
 {
     dim3 grid((unsigned)a.m, (unsigned)a.qb);
-    hipLaunchKernelGGL((k_select_rc<NOTION, EXACT, VPT>), grid, dim3(kT), 0, st, a.S, a.n, a.m,
-                       a.ldm, a.cq, a.eq, a.X, a.d, a.Z, a.UT, a.Dj, a.stats);
+    hipLaunchKernelGGL((k_select_rc<NOTION, EXACT, VPT, G, CAP, STG>), grid, dim3(G::kN), 0, st, a.S,
+                       a.n, a.m, a.ldm, a.cq, a.eq, a.X, a.d, a.Z, a.UT, a.Dj, a.stats);
     return hipGetLastError();
 }
 
+// Columns up to 64 x 128 values: one wave (no block barriers; the fixed
+// per-column work, sampling, bracket and scans, done once), in registers; up
+// to 128 x 128: two waves, in registers; longer: four waves streaming from
+// memory.  The register budgets keep two or three waves per SIMD.
 template <int NOTION, bool EXACT>
 hipError_t launch_rc_vpt(const SelectRcArgs &a, hipStream_t st)
 {
-    const int64_t vpt = (a.n + kT - 1) / kT;
-    if (vpt <= 4) return launch_rc<NOTION, EXACT, 4>(a, st);
-    if (vpt <= 8) return launch_rc<NOTION, EXACT, 8>(a, st);
-    if (vpt <= 16) return launch_rc<NOTION, EXACT, 16>(a, st);
-    if (vpt <= 24) return launch_rc<NOTION, EXACT, 24>(a, st);
-    if (vpt <= 32) return launch_rc<NOTION, EXACT, 32>(a, st);
-    if (vpt <= 40) return launch_rc<NOTION, EXACT, 40>(a, st);
-    if (vpt <= 48) return launch_rc<NOTION, EXACT, 48>(a, st);
-    if (vpt <= 64) return launch_rc<NOTION, EXACT, 64>(a, st);
-    return launch_rc<NOTION, EXACT, 0>(a, st);
+    const int64_t w = (a.n + 63) / 64;
+    if (w <= 8) return launch_rc<NOTION, EXACT, 8, WaveG, kCapWave, 512>(a, st);
+    if (w <= 16) return launch_rc<NOTION, EXACT, 16, WaveG, kCapWave, 512>(a, st);
+    if (w <= 32) return launch_rc<NOTION, EXACT, 32, WaveG, kCapWave, 512>(a, st);
+    if (w <= 64) return launch_rc<NOTION, EXACT, 64, WaveG, kCapWave, 512>(a, st);
+    if (w <= 96) return launch_rc<NOTION, EXACT, 96, WaveG, kCapWave, 512>(a, st);
+    if (w <= 128) return launch_rc<NOTION, EXACT, 128, WaveG, kCapWave, 512>(a, st);
+    const int64_t p = (a.n + 127) / 128;
+    if (p <= 80) return launch_rc<NOTION, EXACT, 80, BlockG<2>, kCapPair, 1024>(a, st);
+    if (p <= 128) return launch_rc<NOTION, EXACT, 128, BlockG<2>, kCapPair, 1024>(a, st);
+    return launch_rc<NOTION, EXACT, 0, BlockG<4>, kCapW, 64>(a, st);
 }
 
 }  // namespace

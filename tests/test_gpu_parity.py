@@ -276,7 +276,7 @@ def test_mfma_depth_parity(prec, notion, n, d, law):
 
 @pytest.mark.parametrize("prec", MFMA_EXACT)
 @pytest.mark.parametrize("notion", ["projection", "apd"])
-@pytest.mark.parametrize("n", [1, 2, 3, 4, 63, 513, 20001])
+@pytest.mark.parametrize("n", [1, 2, 3, 4, 63, 513, 6000, 8193, 10000, 16384, 20001])
 def test_mfma_depth_tiny_ragged_and_long(prec, notion, n):
     w = workloads.small(notion, n, 4, 5, 60, 3, 0.5, law="gaussian", seed_cfg=n + 17)
     _compare(notion, w, precision=prec)
@@ -399,5 +399,39 @@ def test_select_recovers_when_samples_mislead(prec, notion):
     X = w.X.copy()
     pos = [((2 * t + 1) * n) // 128 for t in range(64)]
     X[pos] = 1e3 * np.sign(np.random.default_rng(5).standard_normal((64, 4)))
+    w.X = X
+    _compare(notion, w, precision=prec)
+
+
+def _register_sample_rows(n):
+    """Rows whose projections the register-resident selects take as their 64
+    bracket samples: slot s of a group of g threads (one wave for n <= 8192,
+    two up to 16384) reads register u = (2 (s // 8) + 1) V // 16 of thread
+    64 (s // (64 // w)) + s % (64 // w), entry thread + g u."""
+    if n <= 64 * 128:
+        waves, g = 1, 64
+        v = next(b for b in (8, 16, 32, 64, 96, 128) if n <= 64 * b)
+    else:
+        waves, g = 2, 128
+        v = next(b for b in (80, 128) if n <= 128 * b)
+    per = 64 // waves
+    rows = []
+    for slot in range(64):
+        tid = 64 * (slot // per) + slot % per
+        rows.append(tid + g * (((2 * (slot >> 3) + 1) * v) // 16))
+    return [r for r in rows if r < n]
+
+
+@pytest.mark.parametrize("prec", ["f32", "bf16"])
+@pytest.mark.parametrize("notion", ["projection", "apd"])
+@pytest.mark.parametrize("n", [6000, 10000])
+def test_register_select_recovers_when_samples_mislead(prec, notion, n):
+    """Outliers planted on the rows the register-resident selects sample make
+    their bracket useless; the column must fall through to the streamed
+    select of the same kernel and still give the exact depths."""
+    w = workloads.small(notion, n, 4, 4, 40, 2, 0.5, law="gaussian", seed_cfg=98)
+    X = w.X.copy()
+    rows = _register_sample_rows(n)
+    X[rows] = 1e3 * np.sign(np.random.default_rng(6).standard_normal((len(rows), 4)))
     w.X = X
     _compare(notion, w, precision=prec)
