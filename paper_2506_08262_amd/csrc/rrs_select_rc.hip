@@ -89,6 +89,7 @@ struct alignas(16) RcShared {
     double cval[CAP];
     uint32_t kmin, kmax;         // order keys of the column's range
     uint32_t ncand, nlow;
+    uint32_t wcnt[2], wlow[2];   // per-wave candidate counts (one or two waves)
     uint32_t count;
     double resA, resB;
     uint32_t sel_bucket, sel_before, sel_count;
@@ -647,9 +648,12 @@ __device__ __forceinline__ bool rc_select(const Col &C, const SRC &src, double m
             const float fA = (float)bA;
             // candidates binned below bin A (t < bA is the histogram pass's
             // test, the same fma) are counted apart
-            uint32_t nc, nlow;
-            if (G::kWaves == 1) {
-                // one wave: slots from ballots, counts in scalar registers
+            uint32_t nc, nlow, nc0;
+            if (G::kWaves <= 2) {
+                // one or two waves: slots from ballots, counts in scalar
+                // registers; wave 0 fills cidx upwards from 0, wave 1
+                // downwards from kCap - 1 (candidate p >= nc0 of the
+                // combined list sits at kCap - 1 - (p - nc0))
                 uint32_t wc = 0, wl = 0;
                 src.each([&](int i, float sv) {
                     const float x = approx_v<PH>(sv, sigf);
@@ -657,19 +661,24 @@ __device__ __forceinline__ bool rc_select(const Col &C, const SRC &src, double m
                     const uint64_t mask = __ballot(in);
                     if (mask) {
                         const uint64_t ml = __ballot(in && fmaf(x, scale, off) < fA);
-                        const uint32_t p =
+                        const uint32_t q =
                             wc + __builtin_amdgcn_mbcnt_hi(
                                      (uint32_t)(mask >> 32),
                                      __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
-                        if (in && p < kCap) sh.cidx[p] = (uint32_t)i;
+                        if (in && q < kCap) sh.cidx[wave == 0 ? q : kCap - 1 - q] = (uint32_t)i;
                         wc += (uint32_t)__popcll(mask);
                         wl += (uint32_t)__popcll(ml);
                     }
                 });
-                if (lane == 0) sh.ncand = wc;  // read by the APD count
-                nc = wc;
-                nlow = wl;
+                if (lane == 0) {
+                    sh.wcnt[wave] = wc;
+                    sh.wlow[wave] = wl;
+                }
                 G::sync();
+                nc0 = sh.wcnt[0];
+                nc = G::kWaves == 2 ? nc0 + sh.wcnt[1] : nc0;
+                nlow = G::kWaves == 2 ? sh.wlow[0] + sh.wlow[1] : sh.wlow[0];
+                if (tid == 0) sh.ncand = nc;  // read by the APD count
             } else {
                 src.each([&](int i, float sv) {
                     const float x = approx_v<PH>(sv, sigf);
@@ -683,44 +692,46 @@ __device__ __forceinline__ bool rc_select(const Col &C, const SRC &src, double m
                 G::sync();
                 nc = sh.ncand;
                 nlow = sh.nlow;
+                nc0 = nc;
             }
             // points below the window: those binned below bin A that are not
             // candidates (a non-candidate under bin A lies below wlo)
             const uint64_t B = (uint64_t)beforeA - nlow;
             fast = nc <= kCap && B <= k && k + (pair ? 1 : 0) < B + nc;
             if (fast) {
-                // the all-pairs ranking counts into cidx[p] (below) and
-                // cidx[kCap / 2 + p] (at most); each thread clears the slots
-                // of the candidate whose index it has just read
                 const bool quad = nc <= kQuadG;
+                // index of candidate p in the collection layout
+                auto cand = [&](uint32_t p) -> int64_t {
+                    return (int64_t)sh.cidx[p < nc0 ? p : kCap - 1 - (p - nc0)];
+                };
                 const uint32_t dd = (uint32_t)C.d, nd = nc * dd;
                 if (EXACT && nd <= (uint32_t)SH::kStage) {
                     // the candidates' rows in one cooperative round of loads
                     // (coordinate c of candidate p at xs[p d + c]), then each
                     // thread runs its candidate's fma chain from LDS
+                    // e / dd = umulhi(e, ceil(2^32 / dd)) for e < 2^16 (d > 1)
+                    const uint32_t rcp = 0xFFFFFFFFu / dd + 1u;
                     for (uint32_t e = tid; e < nd; e += G::kN) {
-                        const uint32_t p = e / dd, c = e - p * dd;
-                        sh.xs[e] = C.X[(int64_t)sh.cidx[p] * C.d + c];
+                        const uint32_t p = dd == 1u ? e : __umulhi(e, rcp), c = e - p * dd;
+                        sh.xs[e] = C.X[cand(p) * C.d + c];
                     }
                     G::sync();
-                    for (uint32_t p = tid; p < nc; p += G::kN) {
-                        if (quad) {
-                            sh.cidx[p] = 0u;
-                            sh.cidx[kCap / 2 + p] = 0u;
-                        }
+                    for (uint32_t p = tid; p < nc; p += G::kN)
                         sh.cval[p] = exact_v<PH>(row_t(sh.xs + p * dd, C), med);
-                    }
                 } else {
-                    for (uint32_t p = tid; p < nc; p += G::kN) {
-                        const int64_t i = (int64_t)sh.cidx[p];
-                        if (quad) {
-                            sh.cidx[p] = 0u;
-                            sh.cidx[kCap / 2 + p] = 0u;
-                        }
-                        sh.cval[p] = exact_v<PH>(exact_t<EXACT>(C, i), med);
-                    }
+                    for (uint32_t p = tid; p < nc; p += G::kN)
+                        sh.cval[p] = exact_v<PH>(exact_t<EXACT>(C, cand(p)), med);
                 }
                 G::sync();
+                if (quad) {
+                    // the all-pairs ranking counts into cidx[p] (below) and
+                    // cidx[kCap / 2 + p] (at most)
+                    for (uint32_t p = tid; p < nc; p += G::kN) {
+                        sh.cidx[p] = 0u;
+                        sh.cidx[kCap / 2 + p] = 0u;
+                    }
+                    G::sync();
+                }
                 const uint64_t rA = k - B, rB = k + 1 - B;
                 if (quad) {
                     // candidate p against a slice of the others, G slices
