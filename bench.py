@@ -41,6 +41,47 @@ WORKLOADS = {
 }
 
 
+def kernel_sources_hash() -> str:
+    """sha256 (first 16 hex digits) of the HIP sources and headers of librrs:
+    recorded HBM traffic is used only while the kernels are unchanged."""
+    import hashlib
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2506_08262_amd", "csrc")
+    for f in sorted(os.listdir(csrc)):
+        if f.endswith((".hip", ".hpp")):
+            h.update(f.encode())
+            with open(os.path.join(csrc, f), "rb") as fh:
+                h.update(fh.read())
+    with open(os.path.join(ROOT, "include", "rrs.h"), "rb") as fh:
+        h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def recorded_traffic(kernel: str, workload: str, precision: str):
+    """HBM bytes per launch of `kernel` on this workload from the rocprofv3
+    counter runs summarised under profiles/ (FETCH_SIZE and WRITE_SIZE, each
+    scaled by what the counter reads for a copy of known size), or None when
+    there is no record or the kernel sources changed since it was taken."""
+    pdir = os.path.join(ROOT, "profiles")
+    if not os.path.isdir(pdir):
+        return None
+    cur = kernel_sources_hash()
+    for f in sorted(os.listdir(pdir)):
+        if not f.endswith(".md"):
+            continue
+        with open(os.path.join(pdir, f)) as fh:
+            for ln in fh:
+                if not ln.startswith("traffic-record:"):
+                    continue
+                kv = dict(t.split("=", 1) for t in ln.split(":", 1)[1].split() if "=" in t)
+                if (kv.get("kernel") == kernel and kv.get("workload") == workload
+                        and kv.get("precision") == precision and kv.get("sources") == cur):
+                    return {"bytes": float(kv["fetch_bytes"]) + float(kv["write_bytes"]),
+                            "fetch_bytes": float(kv["fetch_bytes"]),
+                            "write_bytes": float(kv["write_bytes"]), "record": f"profiles/{f}"}
+    return None
+
+
 def kernel_model(name: str, notion: str, d: int, precision: str = "f64"):
     """Algorithmic cost per work unit of each kernel (bytes or flops the method needs)."""
     if name == "k_gemm" and notion != "halfspace":
@@ -277,6 +318,13 @@ def main():
                     "peak": model["peak"], "unit": model["unit"], "frac": achieved / model["peak"],
                     "traffic": None, "avg_launch_ms": st["avg_ms"],
                     "units_per_launch": units_per_launch, "per_unit": model["what"]}
+            rec = recorded_traffic(name, args.workload, args.precision)
+            if rec is not None:
+                # HBM bytes per launch (counter runs), beside the algorithmic bytes
+                roof["traffic"] = rec["bytes"]
+                roof["traffic_detail"] = rec
+                if model["unit"] == "GB/s":
+                    roof["algorithmic_bytes"] = model["per_unit"] * units_per_launch
             if "issued_per_unit" in model:
                 roof["issued_frac"] = (model["issued_per_unit"] * units_per_launch
                                        / (st["avg_ms"] * 1e-3) * 1e-12 / model["peak"])
