@@ -227,12 +227,11 @@ rrs_status run(int notion, const double *X, int64_t n, int64_t d, const double *
     RRS_HIP_TRY(hipStreamSynchronize(st));
     if (g_prof.on) {
         g_prof.collect();
-        std::vector<uint32_t> hs(rrs::kStatWords);
-        RRS_HIP_TRY(hipMemcpy(hs.data(), stats, hs.size() * 4, hipMemcpyDeviceToHost));
-        for (int s = 0; s < rrs::kStatSpread; ++s)
-            g_prof.sel_fallback += hs[16 + (rrs::kStatSpread + s) * rrs::kStatStride];
+        uint32_t hs[6] = {0, 0, 0, 0, 0, 0};
+        RRS_HIP_TRY(hipMemcpy(hs, stats, sizeof(hs), hipMemcpyDeviceToHost));
+        g_prof.sel_fallback += hs[1];
         uint64_t rp = 0;
-        std::memcpy(&rp, hs.data() + 4, sizeof(rp));
+        std::memcpy(&rp, hs + 4, sizeof(rp));
         g_prof.recheck_pairs += (double)rp;
     }
     return RRS_OK;

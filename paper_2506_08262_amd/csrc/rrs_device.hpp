@@ -17,12 +17,8 @@
 
 namespace rrs {
 
-// One count of kind 0 / 1 into the spread select counters (profiling only).
-__device__ __forceinline__ void stat_count(uint32_t *stats, int kind)
-{
-    const unsigned slot = (blockIdx.x + 7u * blockIdx.y) & (unsigned)(kStatSpread - 1);
-    atomicAdd(&stats[16 + (kind * kStatSpread + (int)slot) * kStatStride], 1u);
-}
+// One select that took the exact fallback (profiling only).
+__device__ __forceinline__ void stat_fallback(uint32_t *stats) { atomicAdd(&stats[1], 1u); }
 
 // ---------------------------------------------------------------------------
 // Philox4x64-10: two 64x64->128 multiplies per round, Weyl key schedule.

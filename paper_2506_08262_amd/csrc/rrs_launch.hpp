@@ -6,13 +6,11 @@
 
 namespace rrs {
 
-// Profiling counters of one job (device, uint32 words): words 0 .. 15 hold
-// single counters (the recheck tally at 4..5); the select's per-column
-// counts (kind 0: window path, 1: exact fallback) are spread over
-// kStatSpread words kStatStride apart per kind, so that one count per
-// workgroup does not serialize a launch on one address.
-constexpr int kStatSpread = 64, kStatStride = 32;
-constexpr int kStatWords = 16 + 2 * kStatSpread * kStatStride;
+// Profiling counters of one job (device, uint32 words): [1] selects that took
+// the exact fallback (rare, so one address suffices), [4..5] the recheck
+// tally (uint64).  Selects that took the window path are counted on the host:
+// one device count per column would serialize a launch on one address.
+constexpr int kStatWords = 16;
 
 
 enum { NOTION_HALFSPACE = 0, NOTION_PROJECTION = 1, NOTION_APD = 2 };

@@ -662,7 +662,7 @@ __device__ void select_pair_stream(const double *__restrict__ col, int64_t n, do
         }
     }
     __syncthreads();
-    if (stats && tid == 0) stat_count(stats, 1);
+    if (stats && tid == 0) stat_fallback(stats);
     const uint64_t A = radix_kth_g<PH>(col, n, med, k, sh);
     a = key_value(A);
     b = a;

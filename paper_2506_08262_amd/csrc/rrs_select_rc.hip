@@ -777,7 +777,7 @@ __device__ __forceinline__ bool rc_select(const Col &C, const SRC &src, double m
         return rc_select<PH, EXACT, G>(C, StreamSrc<G>{C.s, C.n}, med, sig, E, k, pair, a, b,
                                        below, sh, stats);
     }
-    if (stats && tid == 0) stat_count(stats, 1);
+    if (stats && tid == 0) stat_fallback(stats);
     const uint64_t A = rc_radix_kth<PH, EXACT, G>(C, med, k, sh);
     a = key_value(A);
     b = a;
