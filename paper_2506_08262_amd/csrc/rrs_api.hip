@@ -6,6 +6,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <algorithm>
 #include <map>
@@ -37,6 +38,37 @@ struct GraphKey {
     }
 };
 std::map<GraphKey, hipGraphExec_t> g_graphs;
+
+// The library's second stream per device (default priority) and its fork /
+// join events: a large call runs two query halves concurrently.
+struct Side {
+    hipStream_t st = nullptr;
+    hipEvent_t fork = nullptr, join = nullptr;
+};
+std::map<int, Side> g_side;
+
+rrs_status side_stream(int dev, Side **out)
+{
+    Side &sd = g_side[dev];
+    if (!sd.st) {
+        RRS_HIP_TRY(hipStreamCreateWithFlags(&sd.st, hipStreamNonBlocking));
+        RRS_HIP_TRY(hipEventCreateWithFlags(&sd.fork, hipEventDisableTiming));
+        RRS_HIP_TRY(hipEventCreateWithFlags(&sd.join, hipEventDisableTiming));
+    }
+    *out = &sd;
+    return RRS_OK;
+}
+
+// Calls with at least this many projections per refinement (queries x
+// directions x points) split their queries in two halves on two streams;
+// RRS_SPLIT_WORK overrides the threshold (tests force the split with 1).
+constexpr double kSplitWork = 268435456.0;
+
+double split_work()
+{
+    const char *e = std::getenv("RRS_SPLIT_WORK");
+    return (e && *e) ? std::atof(e) : kSplitWork;
+}
 
 void drop_graphs()
 {
@@ -126,6 +158,22 @@ rrs_status run(int notion, const double *X, int64_t n, int64_t d, const double *
     rrs::Plan plan;
     rrs_status ps = rrs::job_plan(s, n, d, limit, &plan);
     if (ps != RRS_OK) return ps;
+    // large calls: two query halves, each with its own workspace and stream;
+    // the queries' refinement chains are independent, so the projection
+    // GEMM of one half overlaps the select of the other (query offsets keep
+    // every direction and result unchanged)
+    int64_t qa = nq;
+    if (!(o.flags & RRS_FLAG_GRAPH) && nq >= 2 &&
+        (double)nq * (double)plan.m * (double)n >= split_work()) {
+        rrs::JobSpec sh = s;
+        sh.nq = nq - nq / 2;
+        rrs::Plan ph;
+        if (rrs::job_plan(sh, n, d, limit / 2, &ph) == RRS_OK) {
+            plan = ph;
+            qa = sh.nq;
+        }
+    }
+    const bool split = qa < nq;
 
     const bool stage_in = !dev_ptrs;
     const bool want_trace = o.trace != nullptr, want_poles = o.poles != nullptr;
@@ -137,6 +185,7 @@ rrs_status run(int notion, const double *X, int64_t n, int64_t d, const double *
     sizes[k++] = stage_in ? (size_t)nq * (8 + 8 + (want_poles ? d * 8 : 0)) : 0;  // outputs
     sizes[k++] = (stage_in && want_trace) ? (size_t)nq * r * 3 * 8 : 0;      // trace
     sizes[k++] = plan.ws_bytes;                                              // job workspace
+    sizes[k++] = split ? plan.ws_bytes : 0;                                  // second half's
     void *base = nullptr;
     rrs_status as = ensure_arena(dev, rrs::carve_size(sizes, k), &base);
     if (as != RRS_OK) return as;
@@ -149,6 +198,7 @@ rrs_status run(int notion, const double *X, int64_t n, int64_t d, const double *
     double *out_poles = cv.take<double>((stage_in && want_poles) ? (size_t)nq * d : 0);
     int64_t *out_trace = cv.take<int64_t>((stage_in && want_trace) ? (size_t)nq * r * 3 : 0);
     void *ws = cv.take<char>(plan.ws_bytes);
+    void *ws2 = cv.take<char>(split ? plan.ws_bytes : 0);
 
     rrs::JobIO io;
     io.Z = Z;
@@ -210,7 +260,34 @@ rrs_status run(int notion, const double *X, int64_t n, int64_t d, const double *
         return RRS_OK;
     }
     RRS_HIP_TRY(rrs::data_prepare(D, data_mem, plan.prec, st));
-    rrs_status es = rrs::enqueue_job(s, D, plan, io, ws, st, &g_prof, &stats);
+    uint32_t *stats2 = nullptr;
+    rrs_status es;
+    if (!split) {
+        es = rrs::enqueue_job(s, D, plan, io, ws, st, &g_prof, &stats);
+    } else {
+        Side *sd = nullptr;
+        const rrs_status ss = side_stream(dev, &sd);
+        if (ss != RRS_OK) return ss;
+        rrs::JobSpec sa = s, sb = s;
+        sa.nq = qa;
+        sb.nq = nq - qa;
+        sb.qoff = s.qoff + qa;
+        rrs::JobIO ib = io;
+        ib.Z = io.Z + qa * d;
+        ib.depth = io.depth + qa;
+        if (io.count) ib.count = io.count + qa;
+        if (io.poles) ib.poles = io.poles + qa * d;
+        if (io.trace) ib.trace = io.trace + qa * (int64_t)r * 3;
+        RRS_HIP_TRY(hipEventRecord(sd->fork, st));
+        RRS_HIP_TRY(hipStreamWaitEvent(sd->st, sd->fork, 0));
+        es = rrs::enqueue_job(sa, D, plan, io, ws, st, &g_prof, &stats);
+        if (es == RRS_OK)
+            es = rrs::enqueue_job(sb, D, plan, ib, ws2, sd->st, &g_prof, &stats2);
+        // join even after a failure: the caller's stream never runs ahead of
+        // work still using the workspace
+        RRS_HIP_TRY(hipEventRecord(sd->join, sd->st));
+        RRS_HIP_TRY(hipStreamWaitEvent(st, sd->join, 0));
+    }
     if (es != RRS_OK) return es;
     if (stage_in) {
         RRS_HIP_TRY(hipMemcpyAsync(depth, out_depth, (size_t)nq * 8, hipMemcpyDeviceToHost, st));
@@ -227,12 +304,15 @@ rrs_status run(int notion, const double *X, int64_t n, int64_t d, const double *
     RRS_HIP_TRY(hipStreamSynchronize(st));
     if (g_prof.on) {
         g_prof.collect();
-        uint32_t hs[6] = {0, 0, 0, 0, 0, 0};
-        RRS_HIP_TRY(hipMemcpy(hs, stats, sizeof(hs), hipMemcpyDeviceToHost));
-        g_prof.sel_fallback += hs[1];
-        uint64_t rp = 0;
-        std::memcpy(&rp, hs + 4, sizeof(rp));
-        g_prof.recheck_pairs += (double)rp;
+        for (uint32_t *sp : {stats, stats2}) {
+            if (!sp) continue;
+            uint32_t hs[6] = {0, 0, 0, 0, 0, 0};
+            RRS_HIP_TRY(hipMemcpy(hs, sp, sizeof(hs), hipMemcpyDeviceToHost));
+            g_prof.sel_fallback += hs[1];
+            uint64_t rp = 0;
+            std::memcpy(&rp, hs + 4, sizeof(rp));
+            g_prof.recheck_pairs += (double)rp;
+        }
     }
     return RRS_OK;
 }

@@ -435,3 +435,20 @@ def test_register_select_recovers_when_samples_mislead(prec, notion, n):
     X[rows] = 1e3 * np.sign(np.random.default_rng(6).standard_normal((len(rows), 4)))
     w.X = X
     _compare(notion, w, precision=prec)
+
+
+@pytest.mark.parametrize("notion,prec", [("halfspace", "f64"), ("halfspace", "bf16"),
+                                         ("projection", "f64"), ("projection", "f32"),
+                                         ("apd", "bf16")])
+def test_two_stream_split_matches_oracle(monkeypatch, notion, prec):
+    """Large calls run two query halves on two streams; forced on a small call
+    with an odd number of queries and a query offset, every output (depths,
+    counts, poles, traces) must equal the oracle's and the unsplit call's."""
+    w = workloads.small(notion, 900, 5, 7, 150, 4, 0.5, law="gaussian", seed_cfg=101)
+    monkeypatch.setenv("RRS_SPLIT_WORK", "1e30")
+    one = rrs.depth(notion, w.X, w.Z, w.K, w.n_refine, w.cap_shrink, w.rrs_seed,
+                    query_offset=3, want_poles=True, want_trace=True, precision=prec)
+    monkeypatch.setenv("RRS_SPLIT_WORK", "1")
+    got, _ = _compare(notion, w, q0=3, precision=prec)
+    for key in ("depth", "poles", "trace") + (("count",) if notion == "halfspace" else ()):
+        assert np.array_equal(got[key], one[key]), key
