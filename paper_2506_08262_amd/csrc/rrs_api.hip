@@ -39,35 +39,48 @@ struct GraphKey {
 };
 std::map<GraphKey, hipGraphExec_t> g_graphs;
 
-// The library's second stream per device (default priority) and its fork /
-// join events: a large call runs two query halves concurrently.
+// The library's extra streams per device (default priority) and their fork /
+// join events: a large call runs its queries in kMaxParts parts concurrently.
+constexpr int kMaxParts = 4;
 struct Side {
-    hipStream_t st = nullptr;
-    hipEvent_t fork = nullptr, join = nullptr;
+    hipStream_t st[kMaxParts - 1] = {};
+    hipEvent_t fork = nullptr, join[kMaxParts - 1] = {};
 };
 std::map<int, Side> g_side;
 
-rrs_status side_stream(int dev, Side **out)
+rrs_status side_streams(int dev, Side **out)
 {
     Side &sd = g_side[dev];
-    if (!sd.st) {
-        RRS_HIP_TRY(hipStreamCreateWithFlags(&sd.st, hipStreamNonBlocking));
+    if (!sd.fork) {
         RRS_HIP_TRY(hipEventCreateWithFlags(&sd.fork, hipEventDisableTiming));
-        RRS_HIP_TRY(hipEventCreateWithFlags(&sd.join, hipEventDisableTiming));
+        for (int i = 0; i < kMaxParts - 1; ++i) {
+            RRS_HIP_TRY(hipStreamCreateWithFlags(&sd.st[i], hipStreamNonBlocking));
+            RRS_HIP_TRY(hipEventCreateWithFlags(&sd.join[i], hipEventDisableTiming));
+        }
     }
     *out = &sd;
     return RRS_OK;
 }
 
 // Calls with at least this many projections per refinement (queries x
-// directions x points) split their queries in two halves on two streams;
-// RRS_SPLIT_WORK overrides the threshold (tests force the split with 1).
+// directions x points) split their queries into parts on separate streams;
+// RRS_SPLIT_WORK overrides the threshold (tests force the split with 1) and
+// RRS_SPLIT_PARTS the number of parts (2 .. 4).  Default: four for halfspace
+// depth (concurrent sign GEMMs keep the matrix cores busier), two otherwise
+// (a projection GEMM overlaps a select; more parts only add contention).
 constexpr double kSplitWork = 268435456.0;
 
 double split_work()
 {
     const char *e = std::getenv("RRS_SPLIT_WORK");
     return (e && *e) ? std::atof(e) : kSplitWork;
+}
+
+int split_parts(int notion)
+{
+    const char *e = std::getenv("RRS_SPLIT_PARTS");
+    const int p = (e && *e) ? std::atoi(e) : (notion == rrs::NOTION_HALFSPACE ? 4 : 2);
+    return p < 2 ? 2 : (p > kMaxParts ? kMaxParts : p);
 }
 
 void drop_graphs()
@@ -162,18 +175,22 @@ rrs_status run(int notion, const double *X, int64_t n, int64_t d, const double *
     // the queries' refinement chains are independent, so the projection
     // GEMM of one half overlaps the select of the other (query offsets keep
     // every direction and result unchanged)
-    int64_t qa = nq;
+    int parts = 1;
+    int64_t qa = nq;  // queries per part (the last part takes the rest)
     if (!(o.flags & RRS_FLAG_GRAPH) && nq >= 2 &&
         (double)nq * (double)plan.m * (double)n >= split_work()) {
+        int p = split_parts(notion);
+        if (p > nq) p = (int)nq;
         rrs::JobSpec sh = s;
-        sh.nq = nq - nq / 2;
+        sh.nq = (nq + p - 1) / p;
         rrs::Plan ph;
-        if (rrs::job_plan(sh, n, d, limit / 2, &ph) == RRS_OK) {
+        if (rrs::job_plan(sh, n, d, limit / (size_t)p, &ph) == RRS_OK) {
             plan = ph;
             qa = sh.nq;
+            parts = (int)((nq + qa - 1) / qa);
         }
     }
-    const bool split = qa < nq;
+    const bool split = parts > 1;
 
     const bool stage_in = !dev_ptrs;
     const bool want_trace = o.trace != nullptr, want_poles = o.poles != nullptr;
@@ -185,7 +202,7 @@ rrs_status run(int notion, const double *X, int64_t n, int64_t d, const double *
     sizes[k++] = stage_in ? (size_t)nq * (8 + 8 + (want_poles ? d * 8 : 0)) : 0;  // outputs
     sizes[k++] = (stage_in && want_trace) ? (size_t)nq * r * 3 * 8 : 0;      // trace
     sizes[k++] = plan.ws_bytes;                                              // job workspace
-    sizes[k++] = split ? plan.ws_bytes : 0;                                  // second half's
+    sizes[k++] = split ? plan.ws_bytes * (size_t)(parts - 1) : 0;           // other parts'
     void *base = nullptr;
     rrs_status as = ensure_arena(dev, rrs::carve_size(sizes, k), &base);
     if (as != RRS_OK) return as;
@@ -198,7 +215,7 @@ rrs_status run(int notion, const double *X, int64_t n, int64_t d, const double *
     double *out_poles = cv.take<double>((stage_in && want_poles) ? (size_t)nq * d : 0);
     int64_t *out_trace = cv.take<int64_t>((stage_in && want_trace) ? (size_t)nq * r * 3 : 0);
     void *ws = cv.take<char>(plan.ws_bytes);
-    void *ws2 = cv.take<char>(split ? plan.ws_bytes : 0);
+    char *ws_rest = cv.take<char>(split ? plan.ws_bytes * (size_t)(parts - 1) : 0);
 
     rrs::JobIO io;
     io.Z = Z;
@@ -221,7 +238,6 @@ rrs_status run(int notion, const double *X, int64_t n, int64_t d, const double *
     D.X = Xd;
     D.n = n;
     D.d = d;
-    uint32_t *stats = nullptr;
     if ((o.flags & RRS_FLAG_GRAPH) && !g_prof.on) {
         // the whole device side as one graph: captured on first use, then replayed
         GraphKey key{};
@@ -260,33 +276,38 @@ rrs_status run(int notion, const double *X, int64_t n, int64_t d, const double *
         return RRS_OK;
     }
     RRS_HIP_TRY(rrs::data_prepare(D, data_mem, plan.prec, st));
-    uint32_t *stats2 = nullptr;
-    rrs_status es;
+    uint32_t *pstats[kMaxParts] = {};
+    rrs_status es = RRS_OK;
     if (!split) {
-        es = rrs::enqueue_job(s, D, plan, io, ws, st, &g_prof, &stats);
+        es = rrs::enqueue_job(s, D, plan, io, ws, st, &g_prof, &pstats[0]);
     } else {
         Side *sd = nullptr;
-        const rrs_status ss = side_stream(dev, &sd);
+        const rrs_status ss = side_streams(dev, &sd);
         if (ss != RRS_OK) return ss;
-        rrs::JobSpec sa = s, sb = s;
-        sa.nq = qa;
-        sb.nq = nq - qa;
-        sb.qoff = s.qoff + qa;
-        rrs::JobIO ib = io;
-        ib.Z = io.Z + qa * d;
-        ib.depth = io.depth + qa;
-        if (io.count) ib.count = io.count + qa;
-        if (io.poles) ib.poles = io.poles + qa * d;
-        if (io.trace) ib.trace = io.trace + qa * (int64_t)r * 3;
         RRS_HIP_TRY(hipEventRecord(sd->fork, st));
-        RRS_HIP_TRY(hipStreamWaitEvent(sd->st, sd->fork, 0));
-        es = rrs::enqueue_job(sa, D, plan, io, ws, st, &g_prof, &stats);
-        if (es == RRS_OK)
-            es = rrs::enqueue_job(sb, D, plan, ib, ws2, sd->st, &g_prof, &stats2);
+        for (int pi = 1; pi < parts; ++pi)
+            RRS_HIP_TRY(hipStreamWaitEvent(sd->st[pi - 1], sd->fork, 0));
+        for (int pi = 0; pi < parts && es == RRS_OK; ++pi) {
+            const int64_t q0 = qa * pi;
+            rrs::JobSpec sp = s;
+            sp.nq = (pi == parts - 1) ? nq - q0 : qa;
+            sp.qoff = s.qoff + q0;
+            rrs::JobIO ip = io;
+            ip.Z = io.Z + q0 * d;
+            ip.depth = io.depth + q0;
+            if (io.count) ip.count = io.count + q0;
+            if (io.poles) ip.poles = io.poles + q0 * d;
+            if (io.trace) ip.trace = io.trace + q0 * (int64_t)r * 3;
+            void *wsp = pi == 0 ? ws : (void *)(ws_rest + plan.ws_bytes * (size_t)(pi - 1));
+            es = rrs::enqueue_job(sp, D, plan, ip, wsp, pi == 0 ? st : sd->st[pi - 1], &g_prof,
+                                  &pstats[pi]);
+        }
         // join even after a failure: the caller's stream never runs ahead of
         // work still using the workspace
-        RRS_HIP_TRY(hipEventRecord(sd->join, sd->st));
-        RRS_HIP_TRY(hipStreamWaitEvent(st, sd->join, 0));
+        for (int pi = 1; pi < parts; ++pi) {
+            RRS_HIP_TRY(hipEventRecord(sd->join[pi - 1], sd->st[pi - 1]));
+            RRS_HIP_TRY(hipStreamWaitEvent(st, sd->join[pi - 1], 0));
+        }
     }
     if (es != RRS_OK) return es;
     if (stage_in) {
@@ -304,7 +325,7 @@ rrs_status run(int notion, const double *X, int64_t n, int64_t d, const double *
     RRS_HIP_TRY(hipStreamSynchronize(st));
     if (g_prof.on) {
         g_prof.collect();
-        for (uint32_t *sp : {stats, stats2}) {
+        for (uint32_t *sp : pstats) {
             if (!sp) continue;
             uint32_t hs[6] = {0, 0, 0, 0, 0, 0};
             RRS_HIP_TRY(hipMemcpy(hs, sp, sizeof(hs), hipMemcpyDeviceToHost));

@@ -44,7 +44,6 @@ namespace {
 
 using namespace sel;
 
-constexpr int kT = 256;
 constexpr int kBins = 256;
 constexpr int kCapW = 2048;      // candidates of one window (workgroup per column)
 constexpr int kCapPair = 1024;   // candidates of one window (two waves per column)

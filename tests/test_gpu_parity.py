@@ -437,14 +437,17 @@ def test_register_select_recovers_when_samples_mislead(prec, notion, n):
     _compare(notion, w, precision=prec)
 
 
+@pytest.mark.parametrize("parts", [2, 4])
 @pytest.mark.parametrize("notion,prec", [("halfspace", "f64"), ("halfspace", "bf16"),
                                          ("projection", "f64"), ("projection", "f32"),
                                          ("apd", "bf16")])
-def test_two_stream_split_matches_oracle(monkeypatch, notion, prec):
-    """Large calls run two query halves on two streams; forced on a small call
-    with an odd number of queries and a query offset, every output (depths,
-    counts, poles, traces) must equal the oracle's and the unsplit call's."""
+def test_two_stream_split_matches_oracle(monkeypatch, notion, prec, parts):
+    """Large calls run their queries in parts on separate streams; forced on a
+    small call with an odd number of queries and a query offset, every output
+    (depths, counts, poles, traces) must equal the oracle's and the unsplit
+    call's."""
     w = workloads.small(notion, 900, 5, 7, 150, 4, 0.5, law="gaussian", seed_cfg=101)
+    monkeypatch.setenv("RRS_SPLIT_PARTS", str(parts))
     monkeypatch.setenv("RRS_SPLIT_WORK", "1e30")
     one = rrs.depth(notion, w.X, w.Z, w.K, w.n_refine, w.cap_shrink, w.rrs_seed,
                     query_offset=3, want_poles=True, want_trace=True, precision=prec)
