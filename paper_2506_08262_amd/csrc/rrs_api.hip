@@ -65,9 +65,10 @@ rrs_status side_streams(int dev, Side **out)
 // Calls with at least this many projections per refinement (queries x
 // directions x points) split their queries into parts on separate streams;
 // RRS_SPLIT_WORK overrides the threshold (tests force the split with 1) and
-// RRS_SPLIT_PARTS the number of parts (2 .. 4).  Default: four for halfspace
-// depth (concurrent sign GEMMs keep the matrix cores busier), two otherwise
-// (a projection GEMM overlaps a select; more parts only add contention).
+// RRS_SPLIT_PARTS the number of parts (1 .. 4).  Default: four for halfspace
+// depth (concurrent sign GEMMs keep the matrix cores busier: -15% on a
+// 1e5 x 100 data set); none for projection / APD depth, where a projection
+// GEMM beside a select gained under 2%.
 constexpr double kSplitWork = 268435456.0;
 
 double split_work()
@@ -79,8 +80,8 @@ double split_work()
 int split_parts(int notion)
 {
     const char *e = std::getenv("RRS_SPLIT_PARTS");
-    const int p = (e && *e) ? std::atoi(e) : (notion == rrs::NOTION_HALFSPACE ? 4 : 2);
-    return p < 2 ? 2 : (p > kMaxParts ? kMaxParts : p);
+    const int p = (e && *e) ? std::atoi(e) : (notion == rrs::NOTION_HALFSPACE ? 4 : 1);
+    return p < 1 ? 1 : (p > kMaxParts ? kMaxParts : p);
 }
 
 void drop_graphs()
@@ -184,7 +185,7 @@ rrs_status run(int notion, const double *X, int64_t n, int64_t d, const double *
         rrs::JobSpec sh = s;
         sh.nq = (nq + p - 1) / p;
         rrs::Plan ph;
-        if (rrs::job_plan(sh, n, d, limit / (size_t)p, &ph) == RRS_OK) {
+        if (p >= 2 && rrs::job_plan(sh, n, d, limit / (size_t)p, &ph) == RRS_OK) {
             plan = ph;
             qa = sh.nq;
             parts = (int)((nq + qa - 1) / qa);
