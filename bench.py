@@ -22,6 +22,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
@@ -301,6 +303,21 @@ def main():
     rrs.rrs_profile_enable(False)
     depth = out["depth"].cpu().numpy()
 
+    err = None
+    if args.precision == "f32_plain":
+        # the approximate form's error against the binary64 result (untimed)
+        ref = fn(X, Z, w.K, w.n_refine, w.cap_shrink, w.rrs_seed, precision="f64")
+        dref = ref["depth"].cpu().numpy()
+        rel = np.abs(depth - dref) / np.maximum(np.abs(dref), 1e-300)
+        err = {"queries": int(depth.size), "queries_differing": int(np.count_nonzero(depth != dref)),
+               "max_rel": float(rel.max()), "mean_rel": float(rel.mean()),
+               "max_abs": float(np.abs(depth - dref).max())}
+        if "count" in out and out["count"] is not None:
+            c = out["count"].cpu().numpy()
+            cr = ref["count"].cpu().numpy()
+            err["count_mismatches"] = int(np.count_nonzero(c != cr))
+            err["max_count_diff"] = int(np.abs(c - cr).max())
+
     sec = (t1 - t0) / args.steps
     proj = w.projections
     value = proj / sec
@@ -374,6 +391,8 @@ def main():
         "counters": counters,
         "depth_mean": float(depth.mean()),
     }
+    if err is not None:
+        line["error_vs_f64"] = err
     print(json.dumps(line), flush=True)
 
 
