@@ -45,7 +45,8 @@ namespace {
 using namespace sel;
 
 constexpr int kBins = 256;
-constexpr int kCapW = 2048;      // candidates of one window (workgroup per column)
+constexpr int kCapW = 1024;      // candidates of one window (four waves, streamed columns;
+                                 // 18 KB of LDS per workgroup keeps seven per CU)
 constexpr int kCapPair = 1024;   // candidates of one window (two waves per column)
 constexpr int kCapWave = 512;    // candidates of one window (wave per column)
 constexpr int kQuad = 512;       // up to this many, rank candidates by all-pairs counts
@@ -946,7 +947,7 @@ hipError_t launch_rc_vpt(const SelectRcArgs &a, hipStream_t st)
     const int64_t p = (a.n + 127) / 128;
     if (p <= 80) return launch_rc<NOTION, EXACT, 80, BlockG<2>, kCapPair, 1024>(a, st);
     if (p <= 128) return launch_rc<NOTION, EXACT, 128, BlockG<2>, kCapPair, 1024>(a, st);
-    return launch_rc<NOTION, EXACT, 0, BlockG<4>, kCapW, 64>(a, st);
+    return launch_rc<NOTION, EXACT, 0, BlockG<4>, kCapW, 64>(a, st);  // n > 16384
 }
 
 }  // namespace
