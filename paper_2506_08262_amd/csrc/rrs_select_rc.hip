@@ -51,7 +51,7 @@ constexpr int kCapPair = 1024;   // candidates of one window (two waves per colu
 constexpr int kCapWave = 512;    // candidates of one window (wave per column)
 constexpr int kQuad = 512;       // up to this many, rank candidates by all-pairs counts
 constexpr int kRadixCand = 64;
-constexpr int kUnroll = 4;
+constexpr int kUnroll = 16;     // loads in flight per lane in the streamed passes
 constexpr int kDs = 128;         // coordinates kept in LDS for the recomputation
 
 // Histogram layout: 64 per-lane slots for values below the bracket, the 256
@@ -238,7 +238,9 @@ __device__ __forceinline__ double exact_v(double t, double med)
 // Where a select reads the column's binary32 projections from.  Both hand
 // every slot to f(i, s_i); slots past n read +inf, which every pass treats as
 // above the bracket and outside the window (live values are finite).
-// StreamSrc: global memory, 4 loads in flight per lane (any n < 2^31).
+// StreamSrc: global memory, kUnroll loads in flight per lane (any n < 2^31):
+// each pass rereads the column from HBM, so the passes need enough bytes in
+// flight to cover its latency.
 template <class G>
 struct StreamSrc {
     static constexpr int kMaxLevel = 6;  // rebracket / narrowing passes allowed
@@ -253,17 +255,17 @@ struct StreamSrc {
     {
         // the trip count is the same for every thread of the group (the
         // one-wave candidate collection counts with ballots)
-        const int nn = (int)n;
-        for (int b = 0; b < nn; b += kUnroll * G::kN) {
-            const int i0 = b + G::tid();
+        for (int64_t b = 0; b < n; b += (int64_t)kUnroll * G::kN) {
+            const int64_t i0 = b + G::tid();
             float t[kUnroll];
 #pragma unroll
             for (int u = 0; u < kUnroll; ++u) {
-                const int i = i0 + u * G::kN;
-                t[u] = i < nn ? __builtin_nontemporal_load(s + i) : __builtin_inff();
+                const int64_t i = i0 + u * G::kN;
+                t[u] = i < n ? __builtin_nontemporal_load(s + i) : __builtin_inff();
             }
+            // slots past n (+inf) never reach a window, so their index is unused
 #pragma unroll
-            for (int u = 0; u < kUnroll; ++u) f(i0 + u * G::kN, t[u]);
+            for (int u = 0; u < kUnroll; ++u) f((int)(i0 + u * G::kN), t[u]);
         }
     }
 };
