@@ -31,9 +31,10 @@
  *
  * Parity status: Philox words, the special functions and the univariate
  * depths are pinned by independent checks in the test suite; the RRS driver
- * is pinned by brute-force exact depth, closed forms and invariants.  The
- * tie-break of the argmin (first index wins, strict improvement only) is a
- * reading of Alg. S3 and is parity unpinned beyond self-consistency.
+ * is pinned by brute-force exact depth, closed forms and invariants, and its
+ * refinement chain (cap schedule, first-index argmin, strict pole update,
+ * initial minimum) by closed forms on symmetric point sets, exact arc minima
+ * in the plane and a replay of Alg. 1 from the pinned building blocks.
  */
 #include <math.h>
 #include <stdint.h>

@@ -1,0 +1,244 @@
+"""Pins of the oracle's refinement chain (Alg. 1 steps 4-6, Alg. S3's scan,
+Alg. S5), on the CPU.
+
+Three independent checks, each chosen so that a plausible misreading fails:
+
+* closed forms on point sets symmetric about the query, where every direction
+  has the same univariate depth: the first index must win every refinement
+  (Alg. S3 scans with a strict '<'), the pole may move only on a strict
+  decrease (Alg. 1 step 5), and the running minimum starts at depth 1
+  (Alg. 1 step 1), so projection depth never moves the pole at all;
+* the exact minimum of the halfspace count over a circular arc in the plane
+  (brute force over the arc's critical angles): refinement 2 draws inside the
+  cap of half-angle (pi/2) alpha around the pole of refinement 1, so its
+  minimum equals the arc minimum in cases where the off-by-one cap
+  (pi/2) alpha^2 cannot reach it;
+* Alg. 1 replayed in Python from the pinned building blocks (directions,
+  projections, univariate depths) with numpy's first-occurrence argmin,
+  compared with the oracle's depth, count, final pole and per-refinement
+  trace, on integer data where many directions tie.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+
+
+def _e1(d):
+    e = np.zeros(d)
+    e[0] = 1.0
+    return e
+
+
+def _symmetric(n_half, d, seed):
+    rng = np.random.default_rng(seed)
+    W = rng.standard_normal((n_half, d))
+    return np.concatenate([W, -W])
+
+
+# --------------------------------------------------------------------------
+# Closed forms: every direction ties.
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("d", [2, 5])
+def test_symmetric_halfspace_first_index_and_strict_update(d):
+    # x and -x for every x, query at the centre: t(-x) = -t(x) exactly, so
+    # every direction counts n/2 on each side (no projection is zero)
+    X = _symmetric(15, d, 3)
+    z = np.zeros(d)
+    n, m, r, alpha, seed, q = len(X), 16, 4, 0.5, 11, 2
+    dep, cnt, pole, tr = oracle.rrs_query("halfspace", X, z, q, m * r, r, alpha, seed)
+    assert cnt == n // 2 and dep == 0.5
+    # first index wins every refinement (all counts tie)
+    assert [j for j, _, _ in tr] == [0] * r
+    # only the first refinement improves on the initial count n
+    assert [imp for _, imp, _ in tr] == [True] + [False] * (r - 1)
+    # so the pole is direction 0 of refinement 1, not of a later refinement
+    u0 = oracle.direction(seed, q, 1, 0, d, 1.0, _e1(d))
+    assert np.array_equal(pole, u0)
+    # a '<=' update would have moved it on to refinement r's direction 0
+    assert not np.array_equal(pole, oracle.direction(seed, q, r, 0, d, alpha ** (r - 1), u0))
+
+
+@pytest.mark.parametrize("notion", ["projection", "apd"])
+def test_symmetric_projection_never_moves_pole(notion):
+    # median of a symmetric column is exactly 0, so every direction has depth
+    # 1 (outlyingness 0), which is the initial minimum: no refinement improves
+    d = 4
+    X = _symmetric(20, d, 5)
+    z = np.zeros(d)
+    dep, _, pole, tr = oracle.rrs_query(notion, X, z, 0, 40, 4, 0.5, 7)
+    assert dep == 1.0
+    assert [j for j, _, _ in tr] == [0] * 4
+    assert [imp for _, imp, _ in tr] == [False] * 4
+    assert np.array_equal(pole, _e1(d))
+
+
+# --------------------------------------------------------------------------
+# The cap schedule: exact arc minima in the plane.
+# --------------------------------------------------------------------------
+def _count_at(W, th):
+    t = W @ np.array([math.cos(th), math.sin(th)])
+    return min(int((t <= 0).sum()), int((t >= 0).sum()))
+
+
+def _arc_min(W, thp, eps):
+    """Exact minimum of the closed-halfspace count over directions at angle
+    in (thp - eps, thp + eps), and the fraction of the arc attaining it.  The
+    count is constant between consecutive critical angles (phi_i +- pi/2)."""
+    phis = np.arctan2(W[:, 1], W[:, 0])
+    crit = np.concatenate([phis + math.pi / 2, phis - math.pi / 2])
+    lo, hi = thp - eps, thp + eps
+    cuts = [lo, hi]
+    for c in crit:
+        for k in range(-3, 4):
+            a = c + 2 * math.pi * k
+            if lo < a < hi:
+                cuts.append(a)
+    cuts = np.sort(cuts)
+    width = {}
+    for a, b in zip(cuts[:-1], cuts[1:]):
+        v = _count_at(W, 0.5 * (a + b))
+        width[v] = width.get(v, 0.0) + (b - a)
+    best = min(width)
+    return best, width[best] / (2 * eps)
+
+
+# (data draw, seed) pairs found by scanning a fixed random sequence: in each
+# the cap (pi/2) alpha around refinement 1's pole contains a strictly lower
+# count than the cap (pi/2) alpha^2 (the off-by-one schedule phi_l = alpha^l)
+_ARC_CASES = [(11, 2), (18, 1), (46, 1), (88, 0)]
+
+
+def _arc_data():
+    rng = np.random.default_rng(7)
+    out = []
+    for _ in range(max(t for t, _ in _ARC_CASES) + 1):
+        X = rng.standard_normal((30, 2))
+        z = rng.standard_normal(2) * 0.7
+        out.append((X, z))
+    return out
+
+
+def test_cap_schedule_reaches_exact_arc_minimum():
+    data = _arc_data()
+    alpha, m, r = 0.5, 40, 3
+    for trial, seed in _ARC_CASES:
+        X, z = data[trial]
+        W = X - z
+        _, _, _, tr = oracle.rrs_query("halfspace", X, z, 0, m * r, r, alpha, seed)
+        p1 = oracle.direction(seed, 0, 1, tr[0][0], 2, 1.0, _e1(2))
+        thp = math.atan2(p1[1], p1[0])
+        right, frac = _arc_min(W, thp, math.pi / 2 * alpha)
+        wrong, _ = _arc_min(W, thp, math.pi / 2 * alpha ** 2)
+        assert right < wrong and frac > 0.02  # the case discriminates
+        # refinement 2 draws inside the cap of half-angle (pi/2) alpha: never
+        # below its exact minimum, and here it attains it
+        assert int(tr[1][2]) == right, (trial, seed)
+
+
+def test_cap_directions_never_leave_the_arc():
+    # lower bound at every refinement l >= 2, for many queries: the minimum of
+    # refinement l is at least the exact minimum over its cap
+    rng = np.random.default_rng(19)
+    alpha, m, r = 0.6, 24, 4
+    for q in range(12):
+        X = rng.standard_normal((25, 2))
+        z = rng.standard_normal(2) * 0.5
+        W = X - z
+        _, _, _, tr = oracle.rrs_query("halfspace", X, z, q, m * r, r, alpha, 4)
+        pole, phi = _e1(2), 1.0
+        for l in range(1, r + 1):
+            j, imp, v = tr[l - 1]
+            if l >= 2:
+                thp = math.atan2(pole[1], pole[0])
+                lo, _ = _arc_min(W, thp, math.pi / 2 * phi)
+                assert int(v) >= lo
+            if imp:
+                pole = oracle.direction(4, q, l, j, 2, phi, pole)
+            phi *= alpha
+
+
+# --------------------------------------------------------------------------
+# Alg. 1 replayed from the pinned building blocks.
+# --------------------------------------------------------------------------
+def _replay(notion, X, z, q, K, r, alpha, seed):
+    n, d = X.shape
+    m = -(-K // r)
+    pole = _e1(d)
+    best = float(n) if notion == "halfspace" else 1.0
+    eps_scale = 1.0  # epsilon_l = (pi/2) alpha^(l-1), carried as alpha^(l-1)
+    trace = []
+    for l in range(1, r + 1):
+        U = [oracle.direction(seed, q, l, j, d, eps_scale, pole) for j in range(m)]
+        vals = []
+        for u in U:
+            t = oracle.project(X, z, u)
+            if notion == "halfspace":
+                vals.append(float(oracle.uni_halfspace(t)))
+            elif notion == "projection":
+                vals.append(oracle.uni_projection(t)[0])
+            else:
+                vals.append(oracle.uni_apd(t)[0])
+        j = int(np.argmin(vals))  # first occurrence of the minimum
+        improved = vals[j] < best
+        if improved:
+            best = vals[j]
+            pole = U[j]
+        trace.append((j, improved, vals[j]))
+        eps_scale = eps_scale * alpha
+    depth = best / n if notion == "halfspace" else best
+    return depth, pole, trace
+
+
+@pytest.mark.parametrize("notion", ["halfspace", "projection", "apd"])
+@pytest.mark.parametrize("r", [2, 3, 4])
+def test_chain_matches_alg1_replay(notion, r):
+    rng = np.random.default_rng(100 + r)
+    d, n = 3, 24
+    # small integers: many directions give equal counts and equal medians
+    X = rng.integers(-3, 4, (n, d)).astype(float)
+    for q in range(3):
+        z = rng.integers(-1, 2, d).astype(float)
+        K = 10 * r
+        dep, cnt, pole, tr = oracle.rrs_query(notion, X, z, q, K, r, 0.5, 9)
+        rd, rpole, rtr = _replay(notion, X, z, q, K, r, 0.5, 9)
+        assert dep == rd
+        if notion == "halfspace":
+            assert cnt == round(rd * n)
+        assert np.array_equal(pole, rpole)
+        for (j, imp, v), (rj, rimp, rv) in zip(tr, rtr):
+            assert (j, imp, v) == (rj, rimp, rv)
+
+
+def test_replay_cases_exercise_ties():
+    # across the replay cases, several directions share a refinement's
+    # minimum (first-index rule) and a refinement's minimum equals the running
+    # minimum without improving it (strict update) -- both many times
+    tied = equal = 0
+    for notion in ("halfspace", "projection", "apd"):
+        for r in (2, 3, 4):
+            rng = np.random.default_rng(100 + r)
+            X = rng.integers(-3, 4, (24, 3)).astype(float)
+            for q in range(3):
+                z = rng.integers(-1, 2, 3).astype(float)
+                m = 10
+                pole, best, phi = _e1(3), (24.0 if notion == "halfspace" else 1.0), 1.0
+                for l in range(1, r + 1):
+                    U = [oracle.direction(9, q, l, j, 3, phi, pole) for j in range(m)]
+                    vals = []
+                    for u in U:
+                        t = oracle.project(X, z, u)
+                        vals.append(float(oracle.uni_halfspace(t)) if notion == "halfspace"
+                                    else (oracle.uni_projection(t)[0] if notion == "projection"
+                                          else oracle.uni_apd(t)[0]))
+                    j = int(np.argmin(vals))
+                    tied += sum(v == vals[j] for v in vals) > 1
+                    equal += vals[j] == best
+                    if vals[j] < best:
+                        best, pole = vals[j], U[j]
+                    phi *= 0.5
+    assert tied >= 10 and equal >= 5
