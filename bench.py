@@ -3,9 +3,9 @@
 A step is one full RRS depth computation (every refinement of every query:
 directions, projection, univariate depth, argmin/pole update) over the
 workload's queries, with X and Z already resident in HBM (device pointers).
-The default workload is projection depth on 10000 x 20 Gaussian data
-(Wishart covariance), 1000 queries (800 in-law, 200 Cauchy), K = 5000,
-r = 20, alpha = 0.5.
+The default workload is halfspace depth on 100,000 x 100 Gaussian-mixture
+data, 500 queries, K = 5000, r = 25, alpha = 0.6, in the bfloat16
+matrix-core form with binary64 recheck (results identical to binary64).
 
 Prints ONE JSON line:
   value     query x direction x point projections per second (whole job)
@@ -13,6 +13,9 @@ Prints ONE JSON line:
             average launch duration measured with HIP events on its launch
             stream during the timed steps
   cpu_baseline  the FP64 oracle on a bounded query sample on the host cores
+  forms     (default workload) the same workload in the plain binary32 form
+            (with its error against binary64) and the binary32 recheck form,
+            and projection depth on the same data (binary32 recheck form)
 """
 from __future__ import annotations
 
@@ -126,11 +129,11 @@ def cpu_model() -> str:
     return "unknown"
 
 
-def cpu_baseline(w, notion, max_queries, per_thread_budget=1.2e8):
+def cpu_baseline(w, notion, max_queries, per_thread_budget=1.2e8, runs=3):
     """The FP64 oracle on a bounded sample of the workload: whole queries when
     one query costs at most `per_thread_budget` projections, else only the
     first refinement (the m sphere directions of l = 1) of each sampled query,
-    which is the same per-projection work."""
+    which is the same per-projection work.  The median of `runs` runs."""
     import numpy as np
 
     import oracle
@@ -140,16 +143,52 @@ def cpu_baseline(w, notion, max_queries, per_thread_budget=1.2e8):
     qs = np.arange(nq)
     full = w.n_refine * w.m_dirs * w.n <= per_thread_budget
     K, r = (w.K, w.n_refine) if full else (w.m_dirs, 1)
-    t0 = time.perf_counter()
-    oracle.rrs_depth_idx(notion, w.X, w.Z[qs], qs, K, r, w.cap_shrink, w.rrs_seed, nthreads=nq)
-    dt = time.perf_counter() - t0
+    times = []
+    for _ in range(runs):
+        t0 = time.perf_counter()
+        oracle.rrs_depth_idx(notion, w.X, w.Z[qs], qs, K, r, w.cap_shrink, w.rrs_seed,
+                             nthreads=nq)
+        times.append(time.perf_counter() - t0)
+    dt = float(np.median(times))
     proj = nq * r * w.m_dirs * w.n
     what = (f"all {w.n_refine} refinements ({w.n_refine * w.m_dirs} directions each)" if full
             else f"refinement 1 only ({w.m_dirs} sphere directions each)")
     return {"value": proj / dt, "unit": "projections/s", "cores": int(nq), "kind": "oracle",
             "sample": f"queries 0..{nq - 1} of {w.nq}, {what}, one OpenMP thread per query, "
-                      f"{proj:.3g} projections in {dt:.1f} s wall on {cpu_model()}",
+                      f"{proj:.3g} projections per run, median of {runs} runs "
+                      f"({', '.join(f'{t:.1f}' for t in times)} s) on {cpu_model()}; "
+                      f"oracle built with {oracle.CFLAGS_TEXT}",
             "seconds": dt}
+
+
+def run_form(fn, X, Z, w, precision, steps):
+    """Times `steps` calls of one precision form (after one warm-up call)."""
+    import torch
+    fn(X, Z, w.K, w.n_refine, w.cap_shrink, w.rrs_seed, precision=precision)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        out = fn(X, Z, w.K, w.n_refine, w.cap_shrink, w.rrs_seed, precision=precision)
+    torch.cuda.synchronize()
+    sec = (time.perf_counter() - t0) / steps
+    return out, sec
+
+
+def error_vs(out, ref):
+    """Error of one form's outputs against the binary64 form's."""
+    depth = out["depth"].cpu().numpy()
+    dref = ref["depth"].cpu().numpy()
+    rel = np.abs(depth - dref) / np.maximum(np.abs(dref), 1e-300)
+    err = {"queries": int(depth.size),
+           "queries_differing": int(np.count_nonzero(depth != dref)),
+           "max_rel": float(rel.max()), "mean_rel": float(rel.mean()),
+           "max_abs": float(np.abs(depth - dref).max())}
+    if out.get("count") is not None:
+        c = out["count"].cpu().numpy()
+        cr = ref["count"].cpu().numpy()
+        err["count_mismatches"] = int(np.count_nonzero(c != cr))
+        err["max_count_diff"] = int(np.abs(c - cr).max())
+    return err
 
 
 def serve_main(args):
@@ -228,12 +267,16 @@ def serve_main(args):
     print(json.dumps(line), flush=True)
 
 
+def sec_main_ms(t0, t1, steps):
+    return (t1 - t0) / steps * 1e3
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="c2", choices=sorted(WORKLOADS) + ["c4"])
+    ap.add_argument("--workload", default="c5h", choices=sorted(WORKLOADS) + ["c4"])
     ap.add_argument("--requests", type=int, default=64, help="c4: requests in the stream")
     ap.add_argument("--max-queries", type=int, default=1000, help="c4: query cap per request")
     ap.add_argument("--slots", type=int, default=4, help="c4: concurrent requests")
@@ -243,6 +286,9 @@ def main():
     ap.add_argument("--precision", default=None, choices=["f64", "f32", "bf16", "f32_plain"],
                     help="projection arithmetic (default: the workload's fastest exact form)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-forms", action="store_true",
+                    help="skip the other precision forms and projection depth on the "
+                         "default workload")
     ap.add_argument("--cpu-queries", type=int, default=32)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run three plain 1 GiB device-to-device copies (reference "
@@ -304,19 +350,32 @@ def main():
     depth = out["depth"].cpu().numpy()
 
     err = None
-    if args.precision == "f32_plain":
-        # the approximate form's error against the binary64 result (untimed)
+    forms = None
+    want_forms = args.workload == "c5h" and not args.no_forms
+    ref = None
+    if args.precision == "f32_plain" or want_forms:
+        # binary64 result of the same workload (untimed): the reference for
+        # the error of the approximate form and the check of the exact ones
+        print("[bench] binary64 reference run ...", file=sys.stderr, flush=True)
         ref = fn(X, Z, w.K, w.n_refine, w.cap_shrink, w.rrs_seed, precision="f64")
-        dref = ref["depth"].cpu().numpy()
-        rel = np.abs(depth - dref) / np.maximum(np.abs(dref), 1e-300)
-        err = {"queries": int(depth.size), "queries_differing": int(np.count_nonzero(depth != dref)),
-               "max_rel": float(rel.max()), "mean_rel": float(rel.mean()),
-               "max_abs": float(np.abs(depth - dref).max())}
-        if "count" in out and out["count"] is not None:
-            c = out["count"].cpu().numpy()
-            cr = ref["count"].cpu().numpy()
-            err["count_mismatches"] = int(np.count_nonzero(c != cr))
-            err["max_count_diff"] = int(np.abs(c - cr).max())
+        torch.cuda.synchronize()
+    if args.precision == "f32_plain":
+        err = error_vs(out, ref)
+    if want_forms:
+        forms = {args.precision: {"ms_per_step": sec_main_ms(t0, t1, args.steps),
+                                  "value": w.projections / ((t1 - t0) / args.steps),
+                                  "identical_to_f64": error_vs(out, ref)["queries_differing"] == 0
+                                  and error_vs(out, ref).get("count_mismatches", 0) == 0}}
+        for prec_name in ("f32_plain", "f32"):
+            print(f"[bench] form {prec_name} ...", file=sys.stderr, flush=True)
+            o2, s2 = run_form(fn, X, Z, w, prec_name, 2)
+            e2 = error_vs(o2, ref)
+            forms[prec_name] = {"ms_per_step": s2 * 1e3, "value": w.projections / s2,
+                                "error_vs_f64": e2}
+        wp = workloads.make("c5", notion="projection")
+        print("[bench] projection depth, same data, f32 ...", file=sys.stderr, flush=True)
+        _, s3 = run_form(rrs.DEPTH_FUNCS["projection"], X, Z, wp, "f32", 1)
+        forms["c5p_projection_f32"] = {"ms_per_step": s3 * 1e3, "value": wp.projections / s3}
 
     sec = (t1 - t0) / args.steps
     proj = w.projections
@@ -393,6 +452,8 @@ def main():
     }
     if err is not None:
         line["error_vs_f64"] = err
+    if forms is not None:
+        line["forms"] = forms
     print(json.dumps(line), flush=True)
 
 

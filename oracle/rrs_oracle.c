@@ -9,7 +9,8 @@
  * shares no code, header, table or constant generator with the GPU library;
  * both sides implement the same written recipe independently.
  *
- * Build: gcc -O2 -ffp-contract=off -fopenmp -shared -fPIC (no -ffast-math).
+ * Build: gcc -O3 -march=x86-64-v3 -ffp-contract=off -fopenmp -shared -fPIC
+ * (no -ffast-math).
  * Every multiply-add that is meant to be fused is written as fma(); all other
  * arithmetic is single IEEE-754 binary64 operations in the order written.
  *

@@ -52,11 +52,19 @@ hipEvent_t Profiler::get()
     return pool[used++];
 }
 
+void Profiler::reserve2()
+{
+    if (used + 2 <= kPoolCap) return;
+    collect();
+}
+
 void Profiler::collect()
 {
     for (const Rec &r : recs) {
         float t = 0.f;
-        if (hipEventElapsedTime(&t, r.a, r.b) == hipSuccess) {
+        // the events may belong to several streams: wait for each end event
+        if (hipEventSynchronize(r.b) == hipSuccess &&
+            hipEventElapsedTime(&t, r.a, r.b) == hipSuccess) {
             launches[r.kind] += 1;
             ms[r.kind] += t;
             work[r.kind] += r.work;
@@ -91,6 +99,7 @@ struct ProfScope {
         if (!p || !p->on) return;
         rec.kind = kind;
         rec.work = work;
+        p->reserve2();
         rec.a = p->get();
         rec.b = p->get();
         if (rec.a && rec.b && hipEventRecord(rec.a, st) == hipSuccess) live = true;

@@ -53,6 +53,9 @@ struct Profiler {
         hipEvent_t a, b;
         double work;
     };
+    // events in flight at most: a long call (thousands of launches) waits
+    // for its recorded launches and reuses their events once the pool is full
+    static constexpr size_t kPoolCap = 256;
     bool on = false;
     std::vector<hipEvent_t> pool;
     size_t used = 0;
@@ -64,6 +67,8 @@ struct Profiler {
     // and those that took the exact fallback (counted on the device)
     double sel_total = 0.0, sel_fallback = 0.0, recheck_pairs = 0.0;
     hipEvent_t get();
+    // makes room for two more events (waits for the recorded launches)
+    void reserve2();
     void collect();
     void clear();
 };
