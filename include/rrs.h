@@ -140,6 +140,32 @@ rrs_status rrs_depth_apd(const double *X, int64_t n, int64_t d,
                          int32_t n_refine, double cap_shrink, uint64_t seed,
                          double *depth, const rrs_opts *opts);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, hosts that forbid allocation inside a call):
+ * rrs_depth_halfspace with the same arguments and results, except that
+ *  - opts is required, with device_ptrs = 1: X, Z, depth, count and the
+ *    optional poles / trace are device memory on the current device;
+ *    flags must be 0 (capture the caller's stream instead of RRS_FLAG_GRAPH);
+ *  - the call only enqueues its work on opts->stream and returns without
+ *    waiting: the outputs are valid once that stream has passed the call;
+ *  - every device buffer the call needs besides the caller's arrays comes from
+ *    a static device array of RRS_NOALLOC_SCRATCH_MIB MiB that each device the
+ *    library runs on holds until the process ends; the call makes no device
+ *    or host allocation (no hipMalloc, hipFree, events or GEMM variant timing,
+ *    and no query split over several streams).
+ * The prepared data (about 8 n d bytes, plus 4 n (d + 16) for the bf16 form)
+ * and the workspace of at least one query must fit the array; queries are
+ * processed in batches that fit.  RRS_E_NOMEM when even one query does not
+ * fit; RRS_E_INVAL as rrs_depth_halfspace, and for missing opts, host
+ * pointers or non-zero flags.  All calls on one device share that device's
+ * array: calls whose work overlaps on one device (several streams or
+ * threads) race and must be serialised by the caller. */
+#define RRS_NOALLOC_SCRATCH_MIB 256
+rrs_status rrs_depth_halfspace_noalloc(const double *X, int64_t n, int64_t d,
+                                       const double *Z, int64_t m, int64_t K,
+                                       int32_t n_refine, double cap_shrink, uint64_t seed,
+                                       double *depth, int64_t *count, const rrs_opts *opts);
+
 /* Text of the last non-OK status returned on this thread ("" if none). */
 const char *rrs_last_error(void);
 

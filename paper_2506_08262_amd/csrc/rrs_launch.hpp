@@ -118,6 +118,9 @@ hipError_t launch_mfma_store(int prec, const void *A0, const void *A1, int64_t n
                              int64_t npad, float *S, hipStream_t st);
 int64_t mfma_col_pad(int64_t ncols);
 hipError_t launch_mfma_gemm(const MfmaArgs &a, hipStream_t st);
+// While suspended (per thread), GEMM launches use the variant already chosen
+// for their key, else variant 0, and never time variants (no events).
+void mfma_tune_suspend(bool on);
 hipError_t launch_mfma_recheck(const MfmaArgs &a, hipStream_t st);
 hipError_t launch_init_state(int64_t qb, int64_t d, int64_t n, double *pole, double *best_d,
                              int64_t *best_c, hipStream_t st);

@@ -1085,6 +1085,8 @@ void tune_store_locked(const TuneKey &k, int v)
     fclose(f);
 }
 
+thread_local bool t_tune_suspended = false;
+
 hipError_t tuned_launch(const GemmLaunch &g, int64_t cnt_words, hipStream_t st)
 {
     const int mode = tune_mode();
@@ -1096,6 +1098,7 @@ hipError_t tuned_launch(const GemmLaunch &g, int64_t cnt_words, hipStream_t st)
         auto it = g_tune.find(key);
         if (it != g_tune.end()) return g.run(it->second, st);
     }
+    if (t_tune_suspended) return g.run(0, st);
     hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
     if (hipStreamIsCapturing(st, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone)
         return g.run(0, st);
@@ -1139,6 +1142,8 @@ hipError_t tuned_launch(const GemmLaunch &g, int64_t cnt_words, hipStream_t st)
 }
 
 }  // namespace
+
+void mfma_tune_suspend(bool on) { t_tune_suspended = on; }
 
 hipError_t launch_mfma_store(int prec, const void *A0, const void *A1, int64_t n, int64_t d,
                              const void *B0, const void *B1, int64_t m, int64_t ncols,

@@ -30,7 +30,7 @@ EXPORTED = ["rrs_depth_halfspace", "rrs_depth_projection", "rrs_depth_apd",
             "rrs_last_error", "rrs_release_workspace", "rrs_version", "rrs_debug_directions",
             "rrs_profile_enable", "rrs_profile_read", "rrs_profile_counter",
             "rrs_ctx_create", "rrs_ctx_destroy", "rrs_dataset_put", "rrs_dataset_release",
-            "rrs_submit", "rrs_wait", "rrs_ctx_get_stats"]
+            "rrs_submit", "rrs_wait", "rrs_ctx_get_stats", "rrs_depth_halfspace_noalloc"]
 
 
 class RRSError(RuntimeError):
@@ -109,6 +109,8 @@ def load(path: str = LIB_PATH):
     common = [p, i64, i64, p, i64, i64, i32, dbl, u64, p]
     L.rrs_depth_halfspace.argtypes = common + [p, ctypes.POINTER(rrs_opts)]
     L.rrs_depth_halfspace.restype = ctypes.c_int
+    L.rrs_depth_halfspace_noalloc.argtypes = common + [p, ctypes.POINTER(rrs_opts)]
+    L.rrs_depth_halfspace_noalloc.restype = ctypes.c_int
     L.rrs_depth_projection.argtypes = common + [ctypes.POINTER(rrs_opts)]
     L.rrs_depth_projection.restype = ctypes.c_int
     L.rrs_depth_apd.argtypes = common + [ctypes.POINTER(rrs_opts)]
@@ -254,6 +256,48 @@ def rrs_depth_apd(X, Z, K, n_refine, cap_shrink, seed=0, precision="f64", query_
     """Asymmetric projection depth of each row of Z; returns dict(depth[, poles, trace])."""
     return _run("rrs_depth_apd", X, Z, K, n_refine, cap_shrink, seed, precision, query_offset,
                 False, want_poles, want_trace, stream, workspace_limit, graph)
+
+
+def rrs_depth_halfspace_noalloc(X, Z, K, n_refine, cap_shrink, seed=0, precision="f64",
+                                query_offset=0, out=None, want_poles=False, want_trace=False,
+                                stream=None, workspace_limit=0):
+    """rrs_depth_halfspace_noalloc: X and Z are torch tensors on the device;
+    the outputs are written into `out` (dict of device tensors depth [m],
+    count [m], optional poles [m, d], trace [m, n_refine, 3]) or into new
+    tensors allocated here by torch (the library allocates nothing).  The
+    call only enqueues the work on `stream` (default: torch's current
+    stream) and returns the output dict at once."""
+    import torch
+    for a, name in ((X, "X"), (Z, "Z")):
+        if not (_is_torch(a) and a.is_cuda and a.dtype == torch.float64 and a.is_contiguous()):
+            raise TypeError(f"{name} must be a contiguous float64 tensor on the device")
+    nq, d = int(Z.shape[0]), int(X.shape[1])
+    if int(Z.shape[1]) != d:
+        raise ValueError("Z must have d columns")
+    if out is None:
+        out = {"depth": torch.empty(nq, dtype=torch.float64, device=X.device),
+               "count": torch.empty(nq, dtype=torch.int64, device=X.device)}
+        if want_poles:
+            out["poles"] = torch.empty((nq, d), dtype=torch.float64, device=X.device)
+        if want_trace:
+            out["trace"] = torch.empty((nq, int(n_refine), 3), dtype=torch.int64,
+                                       device=X.device)
+    o = rrs_opts()
+    o.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+    o.device_ptrs = 1
+    s = stream if stream is not None else torch.cuda.current_stream(X.device)
+    o.stream = ctypes.c_void_p(s.cuda_stream if hasattr(s, "cuda_stream") else int(s))
+    o.query_offset = int(query_offset)
+    o.poles = ctypes.c_void_p(out["poles"].data_ptr()) if "poles" in out else None
+    o.trace = ctypes.c_void_p(out["trace"].data_ptr()) if "trace" in out else None
+    o.workspace_limit = int(workspace_limit or 0)
+    cnt = out.get("count")
+    _check(load().rrs_depth_halfspace_noalloc(
+        ctypes.c_void_p(X.data_ptr()), int(X.shape[0]), d, ctypes.c_void_p(Z.data_ptr()), nq,
+        int(K), int(n_refine), float(cap_shrink), int(seed),
+        ctypes.c_void_p(out["depth"].data_ptr()),
+        ctypes.c_void_p(cnt.data_ptr()) if cnt is not None else None, ctypes.byref(o)))
+    return out
 
 
 DEPTH_FUNCS = {"halfspace": rrs_depth_halfspace, "projection": rrs_depth_projection,
