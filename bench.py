@@ -345,7 +345,7 @@ def main():
     t1 = time.perf_counter()
     prof = rrs.rrs_profile_read()
     counters = {c: rrs.rrs_profile_counter(c)
-                for c in ("select_fast", "select_fallback", "recheck_pairs")}
+                for c in ("select_fast", "select_fallback", "recheck_pairs", "gemm_pairs")}
     rrs.rrs_profile_enable(False)
     depth = out["depth"].cpu().numpy()
 
@@ -389,16 +389,23 @@ def main():
         model = kernel_model(name, notion, w.d, args.precision)
         if model is not None:
             units_per_launch = st["work_units"] / st["launches"]
-            achieved = model["per_unit"] * units_per_launch / (st["avg_ms"] * 1e-3) * model["scale"]
             timing = "per launch: algorithmic cost of one launch / its average HIP-event time"
+            if name == "k_gemm" and notion == "halfspace" and counters.get("gemm_pairs"):
+                # with cap culling the sign GEMM evaluates only the pairs of the
+                # points not decided by the cap bound: its algorithmic work is
+                # those pairs (counted by the library), not every projection
+                units_per_launch = counters["gemm_pairs"] / st["launches"]
+                timing += ("; units = (query, direction, point) pairs the GEMM evaluated "
+                           "(the other projections are decided by the cap bound)")
+            achieved = model["per_unit"] * units_per_launch / (st["avg_ms"] * 1e-3) * model["scale"]
             kernel_ms_per_step = st["total_ms"] / args.steps
             if kernel_ms_per_step > 1.02 * sec * 1e3:
                 # launches of this kernel overlapped (the library split the
                 # queries over streams): per-launch times include the others'
                 # share of the GPU, so rate the kernel over the whole step
                 # instead (a lower bound on its rate)
-                achieved = (model["per_unit"] * st["work_units"] / args.steps / sec
-                            * model["scale"])
+                achieved = (model["per_unit"] * units_per_launch * st["launches"] / args.steps
+                            / sec * model["scale"])
                 timing = (f"aggregate: launches overlapped (sum of launch times "
                           f"{kernel_ms_per_step:.0f} ms per step > step {sec * 1e3:.0f} ms), "
                           f"so the rate is the step's algorithmic cost of this kernel / the step time")
@@ -450,6 +457,11 @@ def main():
         "counters": counters,
         "depth_mean": float(depth.mean()),
     }
+    if counters.get("gemm_pairs"):
+        gp = counters["gemm_pairs"] / args.steps
+        line["cull"] = {"gemm_pairs_per_step": gp, "gemm_fraction": gp / proj,
+                        "what": "pairs the sign GEMM evaluated; the rest were decided by the "
+                                "cap bound of refinements l >= 2 (exact)"}
     if err is not None:
         line["error_vs_f64"] = err
     if forms is not None:

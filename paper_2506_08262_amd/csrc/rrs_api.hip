@@ -77,10 +77,14 @@ double split_work()
     return (e && *e) ? std::atof(e) : kSplitWork;
 }
 
-int split_parts(int notion)
+int split_parts(int notion, int precision)
 {
+    // the bfloat16 halfspace form runs a persistent GEMM that fills the chip
+    // by itself; the other halfspace forms gain from concurrent GEMMs
     const char *e = std::getenv("RRS_SPLIT_PARTS");
-    const int p = (e && *e) ? std::atoi(e) : (notion == rrs::NOTION_HALFSPACE ? 4 : 1);
+    const int dflt =
+        (notion == rrs::NOTION_HALFSPACE && precision != RRS_BF16_RECHECK) ? 4 : 1;
+    const int p = (e && *e) ? std::atoi(e) : dflt;
     return p < 1 ? 1 : (p > kMaxParts ? kMaxParts : p);
 }
 
@@ -180,7 +184,7 @@ rrs_status run(int notion, const double *X, int64_t n, int64_t d, const double *
     int64_t qa = nq;  // queries per part (the last part takes the rest)
     if (!(o.flags & RRS_FLAG_GRAPH) && nq >= 2 &&
         (double)nq * (double)plan.m * (double)n >= split_work()) {
-        int p = split_parts(notion);
+        int p = split_parts(notion, o.precision);
         if (p > nq) p = (int)nq;
         rrs::JobSpec sh = s;
         sh.nq = (nq + p - 1) / p;
@@ -328,12 +332,14 @@ rrs_status run(int notion, const double *X, int64_t n, int64_t d, const double *
         g_prof.collect();
         for (uint32_t *sp : pstats) {
             if (!sp) continue;
-            uint32_t hs[6] = {0, 0, 0, 0, 0, 0};
+            uint32_t hs[8] = {0, 0, 0, 0, 0, 0, 0, 0};
             RRS_HIP_TRY(hipMemcpy(hs, sp, sizeof(hs), hipMemcpyDeviceToHost));
             g_prof.sel_fallback += hs[1];
-            uint64_t rp = 0;
+            uint64_t rp = 0, gp = 0;
             std::memcpy(&rp, hs + 4, sizeof(rp));
+            std::memcpy(&gp, hs + 6, sizeof(gp));
             g_prof.recheck_pairs += (double)rp;
+            g_prof.gemm_pairs += (double)gp;
         }
     }
     return RRS_OK;
@@ -412,6 +418,10 @@ int32_t rrs_profile_counter(const char *name, double *value)
     }
     if (std::strcmp(name, "recheck_pairs") == 0) {
         *value = g_prof.recheck_pairs;
+        return 0;
+    }
+    if (std::strcmp(name, "gemm_pairs") == 0) {
+        *value = g_prof.gemm_pairs;
         return 0;
     }
     return -1;

@@ -8,6 +8,7 @@
 
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 
 namespace rrs {
 
@@ -38,9 +39,9 @@ size_t carve_size(const size_t *sizes, int k)
     return off + 256;
 }
 
-const char *const kKernelNames[K_COUNT] = {"k_gen_dirs",    "k_proj_f64",  "k_select",
-                                           "k_argmin_pole", "k_gemm",      "k_recheck",
-                                           "k_misc"};
+const char *const kKernelNames[K_COUNT] = {"k_gen_dirs",    "k_proj_f64", "k_select",
+                                           "k_argmin_pole", "k_gemm",     "k_recheck",
+                                           "k_misc",        "k_cull"};
 
 hipEvent_t Profiler::get()
 {
@@ -83,10 +84,24 @@ void Profiler::clear()
         ms[k] = 0.0;
         work[k] = 0.0;
     }
-    sel_total = sel_fallback = recheck_pairs = 0.0;
+    sel_total = sel_fallback = recheck_pairs = gemm_pairs = 0.0;
 }
 
 namespace {
+
+bool env_flag(const char *name, bool dflt)
+{
+    const char *e = std::getenv(name);
+    if (!e || !*e) return dflt;
+    return std::atoi(e) != 0;
+}
+
+double env_double(const char *name, double dflt)
+{
+    const char *e = std::getenv(name);
+    if (!e || !*e) return dflt;
+    return std::atof(e);
+}
 
 // HIP events around one launch on its stream (when profiling).
 struct ProfScope {
@@ -216,6 +231,17 @@ int job_sizes(const JobSpec &s, int64_t n, int64_t d, const Plan &p, int64_t qb,
     sz[k++] = (mfma && !half) ? (size_t)qb * p.m * n * 4 : 0;   // S (binary32)
     sz[k++] = (mfma && !half) ? npad * 8 : 0;                   // cq
     sz[k++] = (mfma && !half) ? npad * 8 : 0;                   // eq
+    // cap culling (halfspace bfloat16 form)
+    const size_t npp = p.cull ? (size_t)mfma_col_pad(qb) : 0;
+    sz[k++] = npp * p.kp * p.eb;                                // P0 (pole operands)
+    sz[k++] = npp * p.kp * p.eb;                                // P1
+    sz[k++] = npp * 4;                                          // pmarg
+    sz[k++] = p.cull ? (size_t)qb * 4 : 0;                      // lam
+    sz[k++] = p.cull ? (size_t)qb * 4 : 0;                      // mu
+    sz[k++] = p.cull ? (size_t)qb * n * 4 : 0;                  // lists
+    sz[k++] = p.cull ? (size_t)qb * 4 : 0;                      // lcount
+    sz[k++] = p.cull ? (size_t)qb * 8 : 0;                      // base
+    sz[k++] = p.cull ? (size_t)(qb + 1) * 4 : 0;                // offs
     return k;
 }
 
@@ -242,9 +268,25 @@ rrs_status job_plan(const JobSpec &s, int64_t n, int64_t d, size_t limit, Plan *
         p.eb = mfma_elem_bytes(p.prec);
         p.terms = mfma_terms(p.prec);
     }
+    // the persistent sign GEMM: bfloat16 halfspace form with K up to 128 and
+    // operands addressable with 32-bit offsets (RRS_SIGN=0 selects the
+    // tile-per-workgroup GEMM of rrs_mfma.hip instead)
+    int64_t hi = s.nq < 65535 ? (s.nq > 0 ? s.nq : 1) : 65535;
+    if (s.notion == NOTION_HALFSPACE && sign_supported(p.prec, d) && env_flag("RRS_SIGN", true)) {
+        const double rowb = (double)p.kp * 2.0;
+        const double cols = (double)mfma_col_pad(hi * p.m) + 128.0;
+        if ((double)n * rowb < 2147483648.0 && cols * rowb < 2147483648.0 &&
+            (double)hi * (double)p.m < 2147483648.0) {
+            p.sign = true;
+            // culling's list-mode items must stay below 2^31
+            const double items = (double)hi * ((double)n / 256.0 + 1.0) *
+                                 (double)((p.m + 127) / 128);
+            p.cull = env_flag("RRS_CULL", true) && items < 2147483648.0;
+        }
+    }
     // largest batch whose workspace fits the limit (the size grows with qb)
-    int64_t lo = 1, hi = s.nq < 65535 ? (s.nq > 0 ? s.nq : 1) : 65535;
-    size_t sz[16];
+    int64_t lo = 1;
+    size_t sz[32];
     auto bytes = [&](int64_t qb) {
         Plan t = p;
         t.qcap = (p.prec >= 0 && s.notion == NOTION_HALFSPACE) ? job_qcap(p, n, qb) : 0;
@@ -280,7 +322,7 @@ rrs_status enqueue_job(const JobSpec &s, const DataDev &D, const Plan &p, const 
     const bool profiling = prof && prof->on;
     if (mfma && D.prec != p.prec)
         return fail(RRS_E_INTERNAL, "data set not prepared for matrix-core format %d", p.prec);
-    size_t sz[16];
+    size_t sz[32];
     job_sizes(s, n, d, p, qb, sz);
     Carver cv(ws);
     double *UT = cv.take<double>(sz[0] / 8);
@@ -299,6 +341,17 @@ rrs_status enqueue_job(const JobSpec &s, const DataDev &D, const Plan &p, const 
     float *S32 = cv.take<float>(sz[13] / 4);
     double *cq = cv.take<double>(sz[14] / 8);
     double *eq = cv.take<double>(sz[15] / 8);
+    void *P0 = cv.take<char>(sz[16]);
+    void *P1 = cv.take<char>(sz[17]);
+    float *pmarg = cv.take<float>(sz[18] / 4);
+    float *lam = cv.take<float>(sz[19] / 4);
+    float *mu = cv.take<float>(sz[20] / 4);
+    uint32_t *lists = cv.take<uint32_t>(sz[21] / 4);
+    uint32_t *lcount = cv.take<uint32_t>(sz[22] / 4);
+    uint32_t *base = cv.take<uint32_t>(sz[23] / 4);
+    uint32_t *offs = cv.take<uint32_t>(sz[24] / 4);
+    const int64_t npad_pole = p.cull ? mfma_col_pad(qb) : 0;
+    const double cull_angle = env_double("RRS_CULL_ANGLE", 1.5707963267948966);
     if (stats_out) *stats_out = stats;
     if (profiling) RRS_HIP_TRY(launch_fill_u32(stats, kStatWords, 0u, st));
 
@@ -317,7 +370,51 @@ rrs_status enqueue_job(const JobSpec &s, const DataDev &D, const Plan &p, const 
                 RRS_HIP_TRY(launch_gen_dirs(ga, st));
             }
             ProjArgs pa{D.XT, D.ldx, n, d, Zb, UT, ldm, m, nb, cnt, T, nullptr};
-            if (half && mfma) {
+            if (half && mfma && p.sign) {
+                // bfloat16 form: persistent sign GEMM, with the points of
+                // refinements l >= 2 culled against each query's cap first
+                RRS_HIP_TRY(launch_fill_u32(qctl, 16, 0u, st));
+                RRS_HIP_TRY(launch_mfma_dirs(p.prec, true, UT, d, m, ldm, nb * m, npad, Zb, D.xbar,
+                                             B0, B1, cmarg, D.amax, nullptr, nullptr, st));
+                SignArgs sa{n,     d,     D.A0,  D.A1,   D.anorm, B0,     B1,     cmarg,
+                            npad,  m,     ldm,   nb,     cnt,     queue,  qctl,   p.qcap,
+                            UT,    Zb,    nullptr, nullptr, nullptr, p.rpi};
+                const bool cull_l = p.cull && l >= 2 && 1.5707963267948966 * phi <= cull_angle;
+                if (cull_l) {
+                    RRS_HIP_TRY(launch_mfma_dirs(p.prec, true, pole, d, 1, 1, nb, npad_pole, Zb,
+                                                 D.xbar, P0, P1, pmarg, D.amax, nullptr, nullptr,
+                                                 st));
+                    RRS_HIP_TRY(launch_fill_u32(lcount, nb, 0u, st));
+                    RRS_HIP_TRY(launch_fill_u32(base, nb * 2, 0u, st));
+                    CullArgs ca{pole,  D.xbar, P0,     P1,   pmarg,
+                                npad_pole, lam, mu,   lists, lcount,
+                                base,  offs,
+                                profiling ? (unsigned long long *)(stats + 6) : nullptr};
+                    {
+                        ProfScope ps(prof, K_CULL, (double)nb * (double)n, st);
+                        RRS_HIP_TRY(launch_cull(sa, ca, st));
+                    }
+                    sa.lists = lists;
+                    sa.lcount = lcount;
+                    sa.offs = offs;
+                } else {
+                    RRS_HIP_TRY(launch_fill_u32(cnt, nb * ldm * 2, 0u, st));
+                    if (profiling) prof->gemm_pairs += proj_units;
+                }
+                {
+                    ProfScope ps(prof, K_MFMA, proj_units, st);
+                    RRS_HIP_TRY(launch_sign(sa, st));
+                }
+                {
+                    ProfScope ps(prof, K_RECHECK, 0.0, st);
+                    RRS_HIP_TRY(launch_block_recheck(
+                        sa, D.XT, D.ldx, profiling ? (uint64_t *)(stats + 4) : nullptr, st));
+                }
+                // queue overflow (never expected): recount in binary64
+                RRS_HIP_TRY(launch_queue_overflow(qctl, p.qcap, cnt, nb * ldm * 2, qctl + 1, st));
+                pa.only_if = qctl + 1;
+                RRS_HIP_TRY(launch_proj_f64(pa, true, st));
+            } else if (half && mfma) {
                 RRS_HIP_TRY(launch_fill_u32(cnt, nb * ldm * 2, 0u, st));
                 RRS_HIP_TRY(launch_fill_u32(qctl, 16, 0u, st));
                 RRS_HIP_TRY(launch_mfma_dirs(p.prec, true, UT, d, m, ldm, nb * m, npad, Zb, D.xbar,

@@ -44,7 +44,7 @@ struct Carver {
 size_t carve_size(const size_t *sizes, int k);
 
 // Per-kernel HIP-event timing (kinds as reported by rrs_profile_read).
-enum { K_GEN = 0, K_PROJ, K_SELECT, K_ARGMIN, K_MFMA, K_RECHECK, K_OTHER, K_COUNT };
+enum { K_GEN = 0, K_PROJ, K_SELECT, K_ARGMIN, K_MFMA, K_RECHECK, K_OTHER, K_CULL, K_COUNT };
 extern const char *const kKernelNames[K_COUNT];
 
 struct Profiler {
@@ -66,6 +66,10 @@ struct Profiler {
     // selects issued (two per projection / APD column, counted on the host)
     // and those that took the exact fallback (counted on the device)
     double sel_total = 0.0, sel_fallback = 0.0, recheck_pairs = 0.0;
+    // (query, direction, point) pairs the sign GEMM evaluated: all of them
+    // without culling (counted on the host), the listed points' pairs after
+    // culling (counted on the device, stats words 6..7)
+    double gemm_pairs = 0.0;
     hipEvent_t get();
     // makes room for two more events (waits for the recorded launches)
     void reserve2();
@@ -121,6 +125,10 @@ struct Plan {
     int terms = 0, prec = -1;
     uint64_t qcap = 0;
     size_t ws_bytes = 0;         // workspace of enqueue_job
+    // halfspace bfloat16 form: persistent sign GEMM (rrs_sign.hip) and cap
+    // culling of the refinements l >= 2
+    bool sign = false, cull = false;
+    int rpi = 4;                 // point tiles per list-mode item
 };
 // Chooses the query batch so that the workspace fits `limit` bytes.
 rrs_status job_plan(const JobSpec &s, int64_t n, int64_t d, size_t limit, Plan *p);

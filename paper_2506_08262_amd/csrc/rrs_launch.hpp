@@ -8,7 +8,7 @@ namespace rrs {
 
 // Profiling counters of one job (device, uint32 words): [1] selects that took
 // the exact fallback (rare, so one address suffices), [4..5] the recheck
-// tally (uint64).  Selects that took the window path are counted on the host:
+// tally (uint64), [6..7] the pairs the culled sign GEMM evaluated (uint64).  Selects that took the window path are counted on the host:
 // one device count per column would serialize a launch on one address.
 constexpr int kStatWords = 16;
 
@@ -122,6 +122,53 @@ hipError_t launch_mfma_gemm(const MfmaArgs &a, hipStream_t st);
 // for their key, else variant 0, and never time variants (no events).
 void mfma_tune_suspend(bool on);
 hipError_t launch_mfma_recheck(const MfmaArgs &a, hipStream_t st);
+// Sets *flag when the recheck queue overflowed, and then zeroes the counts
+// (cnt_words words) for the binary64 recount that follows.
+hipError_t launch_queue_overflow(const uint32_t *qcount, uint64_t qcap, uint32_t *cnt,
+                                 int64_t cnt_words, uint32_t *flag, hipStream_t st);
+
+// Persistent sign GEMM and cap culling of the bfloat16 form (rrs_sign.hip).
+constexpr int kSignMaxKS = 8;  // padded K up to 128 (d <= 126)
+struct SignArgs {
+    int64_t n, d;
+    const void *A0, *A1;       // [n][kp] centred data, bf16 hi / lo
+    const float *anorm;        // [n]
+    const void *B0, *B1;       // [npad][kp] direction operands (flat columns q m + j)
+    const float *cmarg;        // [npad]
+    int64_t npad, m, ldm, qb;
+    uint32_t *cnt;             // [qb][ldm][2]
+    uint64_t *queue;
+    uint32_t *qcount;
+    uint64_t qcap;
+    const double *UT;          // [qb][d][ldm] binary64 directions (cull bounds)
+    const double *Z;           // [qb][d]
+    // list mode: the undecided points of each query (null: every point)
+    const uint32_t *lists, *lcount, *offs;
+    int rpi;                   // point tiles of 256 per list-mode item
+};
+struct CullArgs {
+    const double *pole;        // [qb][d] current poles
+    const double *xbar;        // [d]
+    const void *P0, *P1;       // [npad_pole][kp] pole operands (centring folded)
+    const float *pmarg;        // [npad_pole] column part of their margin
+    int64_t npad_pole;
+    float *lam, *mu;           // [qb] cull thresholds
+    uint32_t *lists;           // [qb][n] out: undecided points
+    uint32_t *lcount;          // [qb] out (zeroed by the caller)
+    uint32_t *base;            // [qb][2] out: decided points below / above (zeroed)
+    uint32_t *offs;            // [qb + 1] out: item offsets of the list-mode GEMM
+    unsigned long long *pairs; // optional: adds sum_q lcount_q * m (pairs the GEMM evaluates)
+};
+bool sign_supported(int prec, int64_t d);
+// Sign counts (cnt must hold the starting counts) and the recheck queue.
+hipError_t launch_sign(const SignArgs &a, hipStream_t st);
+// Binary64 recount of the (query, direction, 64-row tile) blocks the sign
+// GEMM queued; adds both counts of every live row.
+hipError_t launch_block_recheck(const SignArgs &a, const double *XT, int64_t ldx,
+                                uint64_t *tally, hipStream_t st);
+// Culls the points of every query against its cap: lists, item offsets, and
+// cnt set to the decided points' counts.
+hipError_t launch_cull(const SignArgs &a, const CullArgs &c, hipStream_t st);
 hipError_t launch_init_state(int64_t qb, int64_t d, int64_t n, double *pole, double *best_d,
                              int64_t *best_c, hipStream_t st);
 hipError_t launch_finalize(int64_t qb, int64_t d, int64_t n, bool half, const double *pole,

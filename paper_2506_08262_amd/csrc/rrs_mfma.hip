@@ -1201,9 +1201,14 @@ hipError_t launch_mfma_recheck(const MfmaArgs &a, hipStream_t st)
                        a.d, a.Z, a.UT, a.ldm, a.cnt, (unsigned long long *)a.tally);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    const int64_t total = a.qb * a.ldm * 2;
-    hipLaunchKernelGGL(k_overflow_reset, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st,
-                       a.qcount, a.qcap, a.cnt, total, a.flag);
+    return launch_queue_overflow(a.qcount, a.qcap, a.cnt, a.qb * a.ldm * 2, a.flag, st);
+}
+
+hipError_t launch_queue_overflow(const uint32_t *qcount, uint64_t qcap, uint32_t *cnt,
+                                 int64_t cnt_words, uint32_t *flag, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_overflow_reset, dim3((unsigned)((cnt_words + 255) / 256)), dim3(256), 0,
+                       st, qcount, qcap, cnt, cnt_words, flag);
     return hipGetLastError();
 }
 
