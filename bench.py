@@ -383,7 +383,8 @@ def main():
 
     # dominant kernel's roofline from its live HIP-event timings
     roof = None
-    dom = max(prof.items(), key=lambda kv: kv[1]["total_ms"]) if prof else None
+    modelled = {k: v for k, v in prof.items() if kernel_model(k, notion, w.d, args.precision)}
+    dom = max(modelled.items(), key=lambda kv: kv[1]["total_ms"]) if modelled else None
     if dom is not None:
         name, st = dom
         model = kernel_model(name, notion, w.d, args.precision)

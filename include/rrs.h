@@ -67,23 +67,28 @@ typedef enum {
     RRS_E_INTERNAL = 6
 } rrs_status;
 
-/* Arithmetic of the projection step.
+/* Arithmetic of the projection step (every notion).
  * RRS_F64: every projection is the binary64 fused multiply-add chain over
  *   coordinates 0..d-1 of the shared recipe, so counts, order statistics and
  *   depths are exact (bit-identical to the FP64 oracle).
- * RRS_F32_RECHECK (halfspace depth only): projections of the mean-centred
- *   data on the matrix cores in binary32 (v_mfma_f32_32x32x2_f32); a sign is
- *   taken from that value only when it exceeds a rigorous error margin,
- *   otherwise the pair is recomputed with the binary64 recipe.  Counts,
- *   depths and the RRS trajectory are identical to RRS_F64.
- * RRS_BF16_RECHECK (halfspace depth only): as RRS_F32_RECHECK, with the
- *   products from two-term bfloat16 splits of the centred data and of the
- *   directions (three bf16 products per K step, binary32 accumulation).
- *   Identical to RRS_F64.
- * RRS_F32_PLAIN (halfspace depth only): the binary32 matrix-core projection
- *   decides every sign by itself (a zero counts on both sides), without
- *   recheck; counts may differ from RRS_F64 where |t| is within the binary32
- *   rounding error, and the trajectory may then differ too.
+ * RRS_F32_RECHECK: projections of the mean-centred data on the matrix cores
+ *   in binary32 (v_mfma_f32_32x32x2_f32).  Halfspace depth takes a sign from
+ *   that value only when it exceeds a rigorous error margin and recomputes
+ *   the pair with the binary64 recipe otherwise; projection and asymmetric
+ *   projection depth locate each order statistic (median, MAD, MAD_+) on the
+ *   binary32 values and recompute only the values inside a rigorous window
+ *   around it in binary64.  Counts, depths and the RRS trajectory are
+ *   identical to RRS_F64.
+ * RRS_BF16_RECHECK: as RRS_F32_RECHECK, with the products from two-term
+ *   bfloat16 splits of the centred data and of the directions (three bf16
+ *   products per K step on v_mfma_f32_32x32x16_bf16, binary32 accumulation).
+ *   Identical to RRS_F64.  For halfspace depth, refinements l >= 2 also cull
+ *   the points whose sign is the same for every direction of the cap (decided
+ *   from the pole's projection and a rigorous bound), which changes no count.
+ * RRS_F32_PLAIN: the binary32 matrix-core projections decide everything by
+ *   themselves (signs, with a zero counting on both sides; order statistics),
+ *   without recheck; results may differ from RRS_F64 where values are within
+ *   the binary32 rounding error, and the trajectory may then differ too.
  * The matrix-core forms need ceil(K / n_refine) < 65536 and m <= 65535. */
 typedef enum {
     RRS_F64 = 0,
@@ -115,6 +120,27 @@ typedef struct {
  * eager calls.  rrs_release_workspace() drops the cached graphs. */
 #define RRS_FLAG_GRAPH 1u
 
+/* flags: RRS_FLAG_FIRST_CAP -- the first refinement draws its directions like
+ * the later ones (Alg. S4, angle-uniform in the cap of half-angle pi/2 around
+ * the initial direction e1), the literal reading of the algorithms' first
+ * cap, instead of uniformly on the whole sphere (Alg. S1, the default; the
+ * main text's description of the first step).  The two agree in law on the
+ * hemisphere only up to the angle-uniform versus area-uniform weighting, and
+ * the hemisphere misses half of the directions D_AP needs (D_AP is not
+ * symmetric under u -> -u).  Provided to study that reading. */
+#define RRS_FLAG_FIRST_CAP 2u
+
+/* flags: RRS_FLAG_AREA_CAP -- the cap directions of refinements l >= 2 (and
+ * of refinement 1 with RRS_FLAG_FIRST_CAP) are uniform in area on the cap
+ * (the polar angle has density proportional to sin^(d-2)) instead of
+ * Alg. S4's angle-uniform law; the polar angle comes from Newton's method on
+ * the cap's area function, computed by a series that converges only below
+ * the hemisphere: RRS_E_INVAL unless cap_shrink <= 0.99 and
+ * RRS_FLAG_FIRST_CAP is off.  Both laws give every direction of the cap
+ * positive density; the paper's text describes the cap as sampled
+ * uniformly. */
+#define RRS_FLAG_AREA_CAP 4u
+
 /* Halfspace (Tukey) depth, Sec. 2: min(#{x_i.u <= z.u}, #{x_i.u >= z.u}) / n,
  * minimised over the RRS directions.  count (may be NULL) receives the
  * integer minimum count per query; depth = count / n. */
@@ -139,6 +165,17 @@ rrs_status rrs_depth_apd(const double *X, int64_t n, int64_t d,
                          const double *Z, int64_t m, int64_t K,
                          int32_t n_refine, double cap_shrink, uint64_t seed,
                          double *depth, const rrs_opts *opts);
+
+/* Mahalanobis depth with the moment estimates, D_M(L) (Sec. "Center-outward
+ * ordering precision and depth benchmark": the closed-form comparator of the
+ * ranking study): (1 + (z - mu)' Sigma^-1 (z - mu))^-1 with mu the mean of X
+ * and Sigma its maximum-likelihood covariance (divisor n), all in binary64 on
+ * the device (covariance and quadratic forms on the FP64 matrix cores).  Not
+ * an RRS depth: no directions.  Memory conventions as the calls above (opts
+ * supplies device_ptrs and stream; flags must be 0); d >= 1.  RRS_E_INVAL
+ * also when the covariance is not positive definite (for example n <= d). */
+rrs_status rrs_depth_mahalanobis(const double *X, int64_t n, int64_t d, const double *Z,
+                                 int64_t m, double *depth, const rrs_opts *opts);
 
 /* For callers that cannot allocate device memory (code under HIP graph
  * capture, tight serving loops, hosts that forbid allocation inside a call):

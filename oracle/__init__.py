@@ -63,6 +63,9 @@ def lib():
         L.o_sincos_halfpi.argtypes = [dbl, p, p]
         L.o_gauss_pair.argtypes = [dbl, dbl, p, p]
         L.o_direction.argtypes = [u64, u64, u64, u64, i64, dbl, p, p]
+        L.o_direction_ex.argtypes = [u64, u64, u64, u64, i64, dbl, p, p, ctypes.c_int,
+                                     ctypes.c_int]
+        L.o_area_cap_angle.argtypes = [dbl, dbl, i64, p, p]
         L.o_project.argtypes = [p, i64, i64, p, p, p]
         L.o_uni_halfspace.argtypes = [p, i64]
         L.o_uni_halfspace.restype = i64
@@ -76,6 +79,9 @@ def lib():
                                   u64, p, p, p, i32]
         L.o_rrs_depth_idx.argtypes = [ctypes.c_int, p, i64, i64, p, i64, p, i64, i32, dbl,
                                       u64, p, p, p, i32]
+        L.o_rrs_depth_idx_mode.argtypes = [ctypes.c_int, p, i64, i64, p, i64, p, i64, i32,
+                                           dbl, u64, p, p, p, i32, ctypes.c_int, ctypes.c_int]
+        L.o_rrs_replay.argtypes = [ctypes.c_int, p, i64, i64, p, u64, i64, i32, dbl, u64, p, p]
         L.o_max_threads.restype = i32
         _lib = L
     return _lib
@@ -122,12 +128,26 @@ def gauss_pair(u1: float, u2: float):
     return a.value, b.value
 
 
-def direction(seed: int, q: int, l: int, j: int, d: int, phi: float, pole) -> np.ndarray:
+def direction(seed: int, q: int, l: int, j: int, d: int, phi: float, pole,
+              first_cap: bool = False, area_cap: bool = False) -> np.ndarray:
     pole = _f64(pole)
     assert pole.shape == (d,)
     u = np.zeros(d, dtype=np.float64)
-    lib().o_direction(int(seed), int(q), int(l), int(j), int(d), float(phi), _ptr(pole), _ptr(u))
+    if first_cap or area_cap:
+        lib().o_direction_ex(int(seed), int(q), int(l), int(j), int(d), float(phi), _ptr(pole),
+                             _ptr(u), 1 if first_cap else 0, 1 if area_cap else 0)
+    else:
+        lib().o_direction(int(seed), int(q), int(l), int(j), int(d), float(phi), _ptr(pole),
+                          _ptr(u))
     return u
+
+
+def area_cap_angle(u: float, phi: float, d: int):
+    """(sin theta, cos theta) of the area-uniform cap angle for uniform u."""
+    s = ctypes.c_double()
+    c = ctypes.c_double()
+    lib().o_area_cap_angle(float(u), float(phi), int(d), ctypes.byref(s), ctypes.byref(c))
+    return s.value, c.value
 
 
 def project(X, z, u) -> np.ndarray:
@@ -208,8 +228,12 @@ def rrs_depth(notion: str, X, Z, K: int, n_refine: int, cap_shrink: float, seed:
 
 
 def rrs_depth_idx(notion: str, X, Z, qidx, K: int, n_refine: int, cap_shrink: float,
-                  seed: int, nthreads: int = 0, with_poles: bool = False):
-    """Depth of every row of Z, row i keyed by stream index qidx[i]."""
+                  seed: int, nthreads: int = 0, with_poles: bool = False,
+                  first_cap: bool = False, area_cap: bool = False):
+    """Depth of every row of Z, row i keyed by stream index qidx[i].  first_cap:
+    the first refinement draws from the pi/2 cap around e1 (Alg. S4) instead of
+    the whole sphere; area_cap: cap directions uniform in area instead of in
+    angle."""
     X = _f64(X)
     Z = _f64(Z)
     n, d = X.shape
@@ -219,15 +243,48 @@ def rrs_depth_idx(notion: str, X, Z, qidx, K: int, n_refine: int, cap_shrink: fl
     depth = np.zeros(nq, dtype=np.float64)
     count = np.zeros(nq, dtype=np.int64)
     poles = np.zeros((nq, d), dtype=np.float64) if with_poles else None
-    lib().o_rrs_depth_idx(NOTIONS[notion], _ptr(X), n, d, _ptr(Z), nq, _ptr(q), int(K),
-                          int(n_refine), float(cap_shrink), int(seed), _ptr(depth), _ptr(count),
-                          _ptr(poles) if with_poles else None, int(nthreads))
+    lib().o_rrs_depth_idx_mode(NOTIONS[notion], _ptr(X), n, d, _ptr(Z), nq, _ptr(q), int(K),
+                               int(n_refine), float(cap_shrink), int(seed), _ptr(depth),
+                               _ptr(count), _ptr(poles) if with_poles else None, int(nthreads),
+                               1 if first_cap else 0, 1 if area_cap else 0)
     out = {"depth": depth}
     if notion == "halfspace":
         out["count"] = count
     if with_poles:
         out["poles"] = poles
     return out
+
+
+def rrs_replay(notion: str, X, z, q: int, K: int, n_refine: int, cap_shrink: float, seed: int,
+               traj) -> np.ndarray:
+    """Exact depths along a given trajectory (rows of traj: chosen index,
+    improved).  Returns [n_refine, 3]: exact minimum over the refinement's
+    directions, exact depth of the chosen direction, first exact argmin."""
+    X = _f64(X)
+    n, d = X.shape
+    z = _f64(z)
+    tr = np.ascontiguousarray(np.asarray(traj, dtype=np.int64)[:, :2])
+    t3 = np.zeros((n_refine, 3), dtype=np.int64)
+    t3[:, :2] = tr
+    out = np.zeros((n_refine, 3), dtype=np.float64)
+    lib().o_rrs_replay(NOTIONS[notion], _ptr(X), n, d, _ptr(z), int(q), int(K), int(n_refine),
+                       float(cap_shrink), int(seed), _ptr(t3), _ptr(out))
+    return out
+
+
+def mahalanobis_depth(X, Z) -> np.ndarray:
+    """D_M(L) of the ranking study (Sec. "Center-outward ordering precision and
+    depth benchmark"): (1 + (z - mu)' Sigma^-1 (z - mu))^-1 with mu the mean of
+    X and Sigma its maximum-likelihood covariance (divisor n); the definition
+    written out in binary64 numpy (mean, covariance, linear solve)."""
+    X = _f64(X)
+    Z = _f64(Z)
+    mu = X.mean(axis=0)
+    A = X - mu
+    S = A.T @ A / X.shape[0]
+    B = Z - mu
+    q = np.sum(B * np.linalg.solve(S, B.T).T, axis=1)
+    return 1.0 / (1.0 + q)
 
 
 def max_threads() -> int:

@@ -21,6 +21,9 @@
  *   - o_gauss_pair ........ N(0,1) variates for Alg. S1 (Box-Muller).
  *   - o_direction ......... Alg. S1 (randomSphere) for the first refinement,
  *                           Alg. S4 (randomSpherePole) for later ones.
+ *   - o_area_cap_angle .... the polar angle of a point uniform in area on a
+ *                           spherical cap (the cap law the main text states;
+ *                           Alg. S4 draws the angle uniformly instead).
  *   - o_project ........... Alg. 2 (ProjParallel) inner loop, on the centred
  *                           point x - z.
  *   - o_uni_halfspace ..... Sec. 2, halfspace depth D_H.
@@ -29,6 +32,11 @@
  *   - o_rrs_query ......... Alg. 1 (classical RRS) with the parallel
  *                           formulation of Alg. 4 / Alg. S5 and the
  *                           sequential tie rule of Alg. S3.
+ *   - o_rrs_replay ........ Alg. 1 steps 3-5 along a given trajectory: the
+ *                           exact univariate depths of each refinement's
+ *                           directions when the poles follow another
+ *                           implementation's choices (test protocol for an
+ *                           approximate projection arithmetic).
  *
  * Parity status: Philox words, the special functions and the univariate
  * depths are pinned by independent checks in the test suite; the RRS driver
@@ -193,7 +201,72 @@ static void o_gaussians(uint64_t seed, uint64_t q, uint64_t l, uint64_t j,
 }
 
 /*
- * Direction j of refinement l (1-based) for query q.
+ * Area-uniform polar angle in a cap (the RRS_FLAG_AREA_CAP reading of "uniform
+ * on the cap"): on S^(d-1) the polar angle theta of a point uniform on the cap
+ * {angle <= eps} has density proportional to sin(theta)^(d-2).  With
+ * x = sin(theta) and the binomial series 1 / sqrt(1 - s^2) = sum_k c_k s^(2k),
+ * c_0 = 1, c_(k+1) = c_k (2k+1) / (2k+2), the mass below theta is
+ * J(x) = int_0^x s^(d-2) / sqrt(1 - s^2) ds = x^(d-1) T(x),
+ * T(x) = sum_k c_k x^(2k) / (d - 1 + 2k).  Inverting J(x) = u J(x_e),
+ * x_e = sin(eps), by Newton's method in y = x / x_e from y = 1 (the function
+ * y^(d-1) T(x_e y) is increasing and convex, so the iterates decrease to the
+ * root), gives sin(theta) = x_e y and cos(theta) = sqrt((1 - x)(1 + x)).
+ * The series stops at the first term at most 2^-60 of the running sum (and
+ * after 200000 terms; accurate to about 1e-10 for eps <= 0.99 pi/2).
+ */
+static void o_cap_series(double x, int64_t n1, double *T, double *R)
+{
+    double x2 = x * x, c = 1.0, p = 1.0, t_sum = 0.0, r_sum = 0.0;
+    for (int64_t k = 0; k < 200000; ++k) {
+        double t = (c * p) / (double)(n1 + 2 * k);
+        t_sum = t_sum + t;
+        r_sum = r_sum + (double)(2 * k) * t;   /* R = x T'(x) */
+        if (t <= 0x1p-60 * t_sum) break;
+        p = p * x2;
+        c = (c * (double)(2 * k + 1)) / (double)(2 * k + 2);
+    }
+    *T = t_sum;
+    *R = r_sum;
+}
+
+static double o_pow_int(double y, int64_t e)
+{
+    double r = 1.0, b = y;
+    while (e > 0) {
+        if (e & 1) r = r * b;
+        e >>= 1;
+        if (e > 0) b = b * b;
+    }
+    return r;
+}
+
+void o_area_cap_angle(double u, double phi, int64_t d, double *st, double *ct)
+{
+    int64_t n1 = d - 1;
+    double xe, ce, Te, Re;
+    o_sincos_halfpi(phi, &xe, &ce);
+    o_cap_series(xe, n1, &Te, &Re);
+    double target = u * Te, y = 1.0;
+    for (int it = 0; it < 200; ++it) {
+        double T, R;
+        o_cap_series(xe * y, n1, &T, &R);
+        double P = o_pow_int(y, n1);
+        double g = P * T - target;
+        double gp = (P / y) * ((double)n1 * T + R);   /* derivative in y */
+        double yn = y - g / gp;
+        if (!(yn < y)) break;
+        y = yn;
+    }
+    double x = xe * y;
+    *st = x;
+    *ct = sqrt((1.0 - x) * (1.0 + x));
+}
+
+/*
+ * Direction j of refinement l (1-based) for query q.  With first_cap, the
+ * first refinement also takes the l >= 2 branch (phi = 1: angle-uniform in
+ * the hemisphere around the initial pole e1), the literal reading of the
+ * algorithms' initial cap of half-angle pi/2.
  *   l == 1 : Alg. S1 -- d Gaussians divided by their Euclidean norm, i.e.
  *            uniform on the whole sphere (the first refinement is a plain
  *            random search; the full sphere keeps D_AP correct because D_AP
@@ -205,10 +278,11 @@ static void o_gaussians(uint64_t seed, uint64_t q, uint64_t l, uint64_t j,
  *            u = v - beta w, w = e1 - p, beta = 2 (w.v) / (w.w)).
  * pole has d entries; u receives d entries.
  */
-void o_direction(uint64_t seed, uint64_t q, uint64_t l, uint64_t j, int64_t d,
-                 double phi, const double *pole, double *u)
+static void o_direction_mode(uint64_t seed, uint64_t q, uint64_t l, uint64_t j, int64_t d,
+                             double phi, const double *pole, double *u, int first_cap,
+                             int area_cap)
 {
-    if (l == 1) {
+    if (l == 1 && !first_cap) {
         o_gaussians(seed, q, l, j, 0, d, u);
         double s = 0.0;
         for (int64_t c = 0; c < d; ++c) s = fma(u[c], u[c], s);
@@ -217,9 +291,13 @@ void o_direction(uint64_t seed, uint64_t q, uint64_t l, uint64_t j, int64_t d,
         return;
     }
     double *v = (double *)malloc(sizeof(double) * (size_t)d);
-    double f = o_uniform(o_word(seed, q, l, j, 0)) * phi;
     double st, ct;
-    o_sincos_halfpi(f, &st, &ct);
+    if (area_cap) {
+        o_area_cap_angle(o_uniform(o_word(seed, q, l, j, 0)), phi, d, &st, &ct);
+    } else {
+        double f = o_uniform(o_word(seed, q, l, j, 0)) * phi;
+        o_sincos_halfpi(f, &st, &ct);
+    }
     o_gaussians(seed, q, l, j, 1, d - 1, v + 1);
     double s = 0.0;
     for (int64_t c = 1; c < d; ++c) s = fma(v[c], v[c], s);
@@ -241,6 +319,20 @@ void o_direction(uint64_t seed, uint64_t q, uint64_t l, uint64_t j, int64_t d,
     u[0] = fma(-beta, a, v[0]);
     for (int64_t c = 1; c < d; ++c) u[c] = fma(beta, pole[c], v[c]);
     free(v);
+}
+
+/* Either first-refinement reading (exported for the pin tests). */
+void o_direction_ex(uint64_t seed, uint64_t q, uint64_t l, uint64_t j, int64_t d, double phi,
+                    const double *pole, double *u, int first_cap, int area_cap)
+{
+    o_direction_mode(seed, q, l, j, d, phi, pole, u, first_cap, area_cap);
+}
+
+/* The generator of the depth calls: refinement 1 on the whole sphere. */
+void o_direction(uint64_t seed, uint64_t q, uint64_t l, uint64_t j, int64_t d,
+                 double phi, const double *pole, double *u)
+{
+    o_direction_mode(seed, q, l, j, d, phi, pole, u, 0, 0);
 }
 
 /* Alg. 2 inner loop on the centred point: t = sum_c (x_c - z_c) u_c,
@@ -347,10 +439,10 @@ enum { O_HALFSPACE = 0, O_PROJECTION = 1, O_APD = 2 };
  * NULL) = final pole; trace (may be NULL) = per refinement
  * {j*, improved, value-of-min as double bits}.
  */
-void o_rrs_query(int notion, const double *X, int64_t n, int64_t d,
-                 const double *z, uint64_t q, int64_t K, int32_t r, double alpha,
-                 uint64_t seed, double *depth, int64_t *count, double *pole_out,
-                 int64_t *trace)
+static void o_rrs_query_mode(int notion, const double *X, int64_t n, int64_t d,
+                             const double *z, uint64_t q, int64_t K, int32_t r, double alpha,
+                             uint64_t seed, double *depth, int64_t *count, double *pole_out,
+                             int64_t *trace, int first_cap, int area_cap)
 {
     int64_t m = (K + r - 1) / r;
     double *pole = (double *)calloc((size_t)d, sizeof(double));
@@ -366,7 +458,8 @@ void o_rrs_query(int notion, const double *X, int64_t n, int64_t d,
         int64_t cbest = 0;
         for (int64_t j = 0; j < m; ++j) {
             double *u = U + j * d;
-            o_direction(seed, q, (uint64_t)l, (uint64_t)j, d, phi, pole, u);
+            o_direction_mode(seed, q, (uint64_t)l, (uint64_t)j, d, phi, pole, u, first_cap,
+                             area_cap);
             o_project(X, n, d, z, u, t);
             if (notion == O_HALFSPACE) {
                 int64_t c = o_uni_halfspace(t, n);
@@ -405,6 +498,64 @@ void o_rrs_query(int notion, const double *X, int64_t n, int64_t d,
     free(t);
 }
 
+void o_rrs_query(int notion, const double *X, int64_t n, int64_t d,
+                 const double *z, uint64_t q, int64_t K, int32_t r, double alpha,
+                 uint64_t seed, double *depth, int64_t *count, double *pole_out,
+                 int64_t *trace)
+{
+    o_rrs_query_mode(notion, X, n, d, z, q, K, r, alpha, seed, depth, count, pole_out, trace, 0,
+                     0);
+}
+
+/* Replay of one query along a trajectory chosen elsewhere (Alg. 1 steps 3-5
+ * with someone else's step-4 decisions): refinement l generates its
+ * directions around the pole the trajectory has reached (e1 at l = 1, then
+ * u_{j*} of every refinement the trajectory marks improved), computes the
+ * exact univariate depth of every direction and reports
+ *   out[3 (l-1) + 0] = the smallest depth over the directions (exact minimum),
+ *   out[3 (l-1) + 1] = the depth of the direction the trajectory chose,
+ *   out[3 (l-1) + 2] = the first index attaining the minimum (as a double).
+ * traj[3 (l-1) + 0] = chosen index j*, traj[3 (l-1) + 1] = improved (0/1).
+ * Halfspace depths are reported as counts / n. */
+void o_rrs_replay(int notion, const double *X, int64_t n, int64_t d, const double *z,
+                  uint64_t q, int64_t K, int32_t r, double alpha, uint64_t seed,
+                  const int64_t *traj, double *out)
+{
+    int64_t m = (K + r - 1) / r;
+    double *pole = (double *)calloc((size_t)d, sizeof(double));
+    double *U = (double *)malloc(sizeof(double) * (size_t)(m * d));
+    double *t = (double *)malloc(sizeof(double) * (size_t)n);
+    double *v = (double *)malloc(sizeof(double) * (size_t)m);
+    pole[0] = 1.0;
+    double phi = 1.0;
+    for (int32_t l = 1; l <= r; ++l) {
+        int64_t jmin = 0;
+        for (int64_t j = 0; j < m; ++j) {
+            double *u = U + j * d;
+            o_direction(seed, q, (uint64_t)l, (uint64_t)j, d, phi, pole, u);
+            o_project(X, n, d, z, u, t);
+            if (notion == O_HALFSPACE)
+                v[j] = (double)o_uni_halfspace(t, n) / (double)n;
+            else if (notion == O_PROJECTION)
+                v[j] = o_uni_projection(t, n, NULL, NULL);
+            else
+                v[j] = o_uni_apd(t, n, NULL, NULL);
+            if (v[j] < v[jmin]) jmin = j;
+        }
+        const int64_t jg = traj[3 * (l - 1) + 0];
+        out[3 * (l - 1) + 0] = v[jmin];
+        out[3 * (l - 1) + 1] = (jg >= 0 && jg < m) ? v[jg] : NAN;
+        out[3 * (l - 1) + 2] = (double)jmin;
+        if (traj[3 * (l - 1) + 1] && jg >= 0 && jg < m)
+            memcpy(pole, U + jg * d, sizeof(double) * (size_t)d);
+        phi = phi * alpha;
+    }
+    free(pole);
+    free(U);
+    free(t);
+    free(v);
+}
+
 /* All queries; queries are independent, spread over nthreads OpenMP threads
  * (nthreads <= 0: the runtime default).  Query i uses stream index q0 + i. */
 void o_rrs_depth(int notion, const double *X, int64_t n, int64_t d,
@@ -432,6 +583,27 @@ int32_t o_max_threads(void)
 #else
     return 1;
 #endif
+}
+
+/* Queries with explicit stream indices qidx[i] (row i of Z), in parallel;
+ * first_cap selects the first-refinement cap reading (see o_direction_mode). */
+void o_rrs_depth_idx_mode(int notion, const double *X, int64_t n, int64_t d,
+                          const double *Z, int64_t nq, const uint64_t *qidx, int64_t K,
+                          int32_t r, double alpha, uint64_t seed, double *depth,
+                          int64_t *count, double *poles, int32_t nthreads, int first_cap,
+                          int area_cap)
+{
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#else
+    (void)nthreads;
+#endif
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t i = 0; i < nq; ++i) {
+        o_rrs_query_mode(notion, X, n, d, Z + i * d, qidx[i], K, r, alpha, seed,
+                         &depth[i], count ? &count[i] : NULL,
+                         poles ? poles + i * d : NULL, NULL, first_cap, area_cap);
+    }
 }
 
 /* Queries with explicit stream indices qidx[i] (row i of Z), in parallel. */

@@ -16,7 +16,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "librrs.so")
 OBJ = os.path.join(HERE, "_build")
 SOURCES = ["rrs_kernels.hip", "rrs_select.hip", "rrs_select_rc.hip", "rrs_mfma.hip",
-           "rrs_sign.hip", "rrs_engine.hip", "rrs_api.hip", "rrs_noalloc.hip",
+           "rrs_sign.hip", "rrs_maha.hip", "rrs_engine.hip", "rrs_api.hip", "rrs_noalloc.hip",
            "rrs_serve.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -152,8 +152,15 @@ rrs_status run(int notion, const double *X, int64_t n, int64_t d, const double *
     rrs_status vs = rrs::job_validate(s, n, d);
     if (vs != RRS_OK) return vs;
     const bool dev_ptrs = o.device_ptrs != 0;
-    if (o.reserved != 0 || (o.flags & ~RRS_FLAG_GRAPH) != 0)
+    if (o.reserved != 0 ||
+        (o.flags & ~(RRS_FLAG_GRAPH | RRS_FLAG_FIRST_CAP | RRS_FLAG_AREA_CAP)) != 0)
         return fail(RRS_E_INVAL, "unknown flags or non-zero reserved field in opts");
+    s.first_cap = (o.flags & RRS_FLAG_FIRST_CAP) != 0;
+    s.area_cap = (o.flags & RRS_FLAG_AREA_CAP) != 0;
+    if (s.area_cap && (s.first_cap || !(alpha <= 0.99)))
+        return fail(RRS_E_INVAL,
+                    "RRS_FLAG_AREA_CAP needs cap_shrink <= 0.99 and no RRS_FLAG_FIRST_CAP (caps "
+                    "below the hemisphere)");
     if ((o.flags & RRS_FLAG_GRAPH) && (!dev_ptrs || o.stream == nullptr))
         return fail(RRS_E_INVAL, "RRS_FLAG_GRAPH needs device pointers and a non-default stream");
     if (!dev_ptrs) {
@@ -250,7 +257,11 @@ rrs_status run(int notion, const double *X, int64_t n, int64_t d, const double *
         double abits = alpha;
         int64_t ab;
         std::memcpy(&ab, &abits, sizeof(ab));
-        const int64_t vals[20] = {notion, o.precision, n, d, nq, K, r, ab, (int64_t)seed,
+        const int64_t vals[20] = {notion,
+                                  o.precision + 256 * (int64_t)s.first_cap +
+                                      512 * (int64_t)s.area_cap,
+                                  n, d, nq, K, r,
+                                  ab, (int64_t)seed,
                                   o.query_offset, (int64_t)X, (int64_t)Z, (int64_t)depth,
                                   (int64_t)count, (int64_t)o.poles, (int64_t)o.trace,
                                   (int64_t)st, (int64_t)base, (int64_t)plan.qb, dev};
@@ -371,6 +382,62 @@ rrs_status rrs_depth_apd(const double *X, int64_t n, int64_t d, const double *Z,
 {
     return run(rrs::NOTION_APD, X, n, d, Z, m, K, n_refine, cap_shrink, seed, depth, nullptr,
                opts);
+}
+
+rrs_status rrs_depth_mahalanobis(const double *X, int64_t n, int64_t d, const double *Z,
+                                 int64_t m, double *depth, const rrs_opts *opts)
+{
+    rrs_opts o{};
+    if (opts) o = *opts;
+    if (m < 0) return fail(RRS_E_INVAL, "number of queries must be >= 0 (got %lld)", (long long)m);
+    if (m == 0) return RRS_OK;
+    if (!X || !Z || !depth) return fail(RRS_E_INVAL, "X, Z and depth must be non-NULL");
+    if (n < 1 || d < 1) return fail(RRS_E_INVAL, "need n >= 1 and d >= 1");
+    if (o.reserved != 0 || o.flags != 0)
+        return fail(RRS_E_INVAL, "rrs_depth_mahalanobis takes no flags");
+    const bool dev_ptrs = o.device_ptrs != 0;
+    if (!dev_ptrs) {
+        if (!all_finite(X, n * d)) return fail(RRS_E_INVAL, "X holds a non-finite value");
+        if (!all_finite(Z, m * d)) return fail(RRS_E_INVAL, "Z holds a non-finite value");
+    }
+    std::lock_guard<std::mutex> lock(g_mutex);
+    int dev = 0;
+    RRS_HIP_TRY(hipGetDevice(&dev));
+    hipStream_t st = (hipStream_t)o.stream;
+    size_t sizes[5];
+    int k = 0;
+    sizes[k++] = rrs::maha_ws_bytes(n, d, m);
+    sizes[k++] = dev_ptrs ? 0 : (size_t)n * d * 8;
+    sizes[k++] = dev_ptrs ? 0 : (size_t)m * d * 8;
+    sizes[k++] = dev_ptrs ? 0 : (size_t)m * 8;
+    void *base = nullptr;
+    rrs_status as = ensure_arena(dev, rrs::carve_size(sizes, k), &base);
+    if (as != RRS_OK) return as;
+    rrs::Carver cv(base);
+    void *ws = cv.take<char>(sizes[0]);
+    double *Xs = cv.take<double>(dev_ptrs ? 0 : (size_t)n * d);
+    double *Zs = cv.take<double>(dev_ptrs ? 0 : (size_t)m * d);
+    double *Ds = cv.take<double>(dev_ptrs ? 0 : (size_t)m);
+    const double *Xd = X, *Zd = Z;
+    double *Dd = depth;
+    if (!dev_ptrs) {
+        RRS_HIP_TRY(hipMemcpyAsync(Xs, X, (size_t)n * d * 8, hipMemcpyHostToDevice, st));
+        RRS_HIP_TRY(hipMemcpyAsync(Zs, Z, (size_t)m * d * 8, hipMemcpyHostToDevice, st));
+        Xd = Xs;
+        Zd = Zs;
+        Dd = Ds;
+    }
+    uint32_t *flag = nullptr;
+    RRS_HIP_TRY(rrs::maha_enqueue(Xd, n, d, Zd, m, Dd, ws, &flag, st));
+    uint32_t hflag = 0;
+    RRS_HIP_TRY(hipMemcpyAsync(&hflag, flag, sizeof(hflag), hipMemcpyDeviceToHost, st));
+    if (!dev_ptrs)
+        RRS_HIP_TRY(hipMemcpyAsync(depth, Ds, (size_t)m * 8, hipMemcpyDeviceToHost, st));
+    RRS_HIP_TRY(hipStreamSynchronize(st));
+    if (hflag)
+        return fail(RRS_E_INVAL, "the covariance of X is not positive definite (n = %lld, d = %lld)",
+                    (long long)n, (long long)d);
+    return RRS_OK;
 }
 
 const char *rrs_last_error(void) { return rrs::last_error().c_str(); }

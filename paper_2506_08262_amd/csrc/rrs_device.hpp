@@ -131,6 +131,72 @@ __device__ __forceinline__ void sincos_halfpi(double f, double &sn, double &cs)
     cs = swap ? s : c;
 }
 
+// Area-uniform polar angle in the cap of half-angle (pi/2) phi in d
+// dimensions: the angle's density is proportional to sin^(d-2), so with
+// x = sin(theta) the distribution function is F = J(x) / J(x_e),
+// J(x) = x^(d-1) T(x), T(x) = sum_k c_k x^(2k) / (d - 1 + 2k),
+// c_0 = 1, c_(k+1) = c_k (2k + 1) / (2k + 2) (the series of 1 / sqrt(1 - x^2)
+// integrated term by term), x_e = sin((pi/2) phi).  For uniform u, Newton's
+// method on g(y) = y^(d-1) T(x_e y) - u T(x_e) from y = 1 (g is increasing
+// and convex, so the iterates decrease monotonically to the root) gives
+// x = x_e y; returns sin(theta) = x and cos(theta) = sqrt((1 - x)(1 + x)).
+// The series stops at the first term below 2^-60 of the sum (at most 200000
+// terms; the calls accept the law only for cap_shrink <= 0.99 and caps below
+// the hemisphere, where this is accurate to about 1e-10).
+__device__ __forceinline__ void cap_series(double x, int64_t n1, double &T, double &R)
+{
+    // T = sum_k t_k, R = sum_k 2k t_k, t_k = c_k x^(2k) / (n1 + 2k)
+    const double x2 = x * x;
+    double c = 1.0, p = 1.0;
+    T = 0.0;
+    R = 0.0;
+    for (int64_t k = 0; k < 200000; ++k) {
+        const double t = (c * p) / (double)(n1 + 2 * k);
+        T = T + t;
+        R = R + (double)(2 * k) * t;
+        if (t <= 0x1p-60 * T) break;
+        p = p * x2;
+        c = (c * (double)(2 * k + 1)) / (double)(2 * k + 2);
+    }
+}
+
+__device__ __forceinline__ double pow_int(double y, int64_t e)
+{
+    double r = 1.0, b = y;
+    while (e > 0) {
+        if (e & 1) r = r * b;
+        e >>= 1;
+        if (e > 0) b = b * b;
+    }
+    return r;
+}
+
+__device__ __forceinline__ void area_cap_angle(double u, double phi, int64_t d, double &st,
+                                               double &ct)
+{
+    const int64_t n1 = d - 1;
+    double xe, ce;
+    sincos_halfpi(phi, xe, ce);
+    double Te, Re;
+    cap_series(xe, n1, Te, Re);
+    const double target = u * Te;
+    double y = 1.0;
+    for (int it = 0; it < 200; ++it) {
+        const double x = xe * y;
+        double T, R;
+        cap_series(x, n1, T, R);
+        const double P = pow_int(y, n1);
+        const double g = P * T - target;
+        const double gp = (P / y) * ((double)n1 * T + R);
+        const double yn = y - g / gp;
+        if (!(yn < y)) break;
+        y = yn;
+    }
+    const double x = xe * y;
+    st = x;
+    ct = sqrt((1.0 - x) * (1.0 + x));
+}
+
 // Box-Muller pair from two stream words.
 __device__ __forceinline__ void gauss_pair(uint64_t w1, uint64_t w2, double &g1, double &g2)
 {

@@ -247,10 +247,14 @@ int job_sizes(const JobSpec &s, int64_t n, int64_t d, const Plan &p, int64_t qb,
 
 uint64_t job_qcap(const Plan &p, int64_t n, int64_t qb)
 {
-    // recheck queue: 1% of the pairs of a launch, at least 1M entries
+    // recheck queue: 1% of the pairs of a launch, at least 1M words;
+    // RRS_QUEUE_WORDS overrides the size (at least 4096 words), e.g. to
+    // exercise the overflow recount
     uint64_t qcap = (uint64_t)qb * (uint64_t)p.m * (uint64_t)n / 100;
     if (qcap < (1u << 20)) qcap = 1u << 20;
     if (qcap > 0xFFFFFFF0ull) qcap = 0xFFFFFFF0ull;
+    const double force = env_double("RRS_QUEUE_WORDS", 0.0);
+    if (force > 0.0) qcap = force < 4096.0 ? 4096u : (force > 4.0e9 ? 4000000000ull : (uint64_t)force);
     return qcap;
 }
 
@@ -364,7 +368,8 @@ rrs_status enqueue_job(const JobSpec &s, const DataDev &D, const Plan &p, const 
         double phi = 1.0;
         for (int32_t l = 1; l <= r; ++l) {
             const double proj_units = (double)nb * (double)m * (double)n;
-            GenArgs ga{d, m, ldm, nb, l, phi, s.seed, (uint64_t)(s.qoff + q0), pole, UT};
+            GenArgs ga{d, m, ldm, nb, l, phi, s.seed, (uint64_t)(s.qoff + q0), pole, UT,
+                       s.first_cap ? 1 : 0, s.area_cap ? 1 : 0};
             {
                 ProfScope ps(prof, K_GEN, (double)nb * m * d, st);
                 RRS_HIP_TRY(launch_gen_dirs(ga, st));
@@ -408,10 +413,11 @@ rrs_status enqueue_job(const JobSpec &s, const DataDev &D, const Plan &p, const 
                 {
                     ProfScope ps(prof, K_RECHECK, 0.0, st);
                     RRS_HIP_TRY(launch_block_recheck(
-                        sa, D.XT, D.ldx, profiling ? (uint64_t *)(stats + 4) : nullptr, st));
+                        sa, D.X, profiling ? (uint64_t *)(stats + 4) : nullptr, st));
                 }
                 // queue overflow (never expected): recount in binary64
-                RRS_HIP_TRY(launch_queue_overflow(qctl, p.qcap, cnt, nb * ldm * 2, qctl + 1, st));
+                RRS_HIP_TRY(launch_queue_overflow(qctl, kSignQueueOverflow - 1u, cnt,
+                                                  nb * ldm * 2, qctl + 1, st));
                 pa.only_if = qctl + 1;
                 RRS_HIP_TRY(launch_proj_f64(pa, true, st));
             } else if (half && mfma) {

@@ -111,6 +111,8 @@ struct JobSpec {
     uint64_t seed = 0;
     int64_t qoff = 0;            // stream index of the first query
     bool want_trace = false;
+    bool first_cap = false;      // RRS_FLAG_FIRST_CAP: refinement 1 in the pi/2 cap of Alg. S4
+    bool area_cap = false;       // RRS_FLAG_AREA_CAP: caps uniform in area
 };
 
 // Validates the arguments of a job on an n x d data set (everything that

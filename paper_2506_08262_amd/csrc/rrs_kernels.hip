@@ -34,7 +34,8 @@ namespace rrs {
 __global__ __launch_bounds__(64) void k_gen_dirs(int64_t d, int64_t m, int64_t ldm, int32_t l,
                                                  double phi, uint64_t seed, uint64_t qbase,
                                                  const double *__restrict__ pole,
-                                                 double *__restrict__ UT)
+                                                 double *__restrict__ UT, int32_t first_cap,
+                                                 int32_t area_cap)
 {
     const int64_t j = (int64_t)blockIdx.x * 64 + threadIdx.x;
     const int64_t qi = blockIdx.y;
@@ -43,9 +44,10 @@ __global__ __launch_bounds__(64) void k_gen_dirs(int64_t d, int64_t m, int64_t l
     const uint64_t ul = (uint64_t)l;
     double *u = UT + qi * d * ldm + j;
 
-    if (l == 1) {
+    if (l == 1 && !first_cap) {
         // Alg. S1: d Gaussians from word pairs (0,1), (2,3), ... then divide
-        // by the Euclidean norm.
+        // by the Euclidean norm.  (first_cap: refinement 1 also draws from
+        // Alg. S4, in the half-angle pi/2 cap around the initial pole e1.)
         double s = 0.0;
         for (int64_t c = 0, b = 0; c < d; c += 4, ++b) {
             const Block4 w = dir_block(seed, q, ul, (uint64_t)j, (uint64_t)b);
@@ -79,7 +81,10 @@ __global__ __launch_bounds__(64) void k_gen_dirs(int64_t d, int64_t m, int64_t l
     // 4k+4 (= word 0 of block k+1).
     Block4 a = dir_block(seed, q, ul, (uint64_t)j, 0);
     double st, ct;
-    sincos_halfpi(uniform_open(a.w0) * phi, st, ct);
+    if (area_cap)
+        area_cap_angle(uniform_open(a.w0), phi, d, st, ct);  // area-uniform in the cap
+    else
+        sincos_halfpi(uniform_open(a.w0) * phi, st, ct);
     double s = 0.0;
     for (int64_t c = 1, b = 0;; c += 4, ++b) {
         if (c > d - 1) break;
@@ -611,7 +616,7 @@ hipError_t launch_gen_dirs(const GenArgs &a, hipStream_t st)
 {
     dim3 grid(ceil_div(a.m, 64), (unsigned)a.qb);
     hipLaunchKernelGGL(k_gen_dirs, grid, dim3(64), 0, st, a.d, a.m, a.ldm, a.l, a.phi, a.seed,
-                       a.qbase, a.pole, a.UT);
+                       a.qbase, a.pole, a.UT, a.first_cap, a.area_cap);
     return hipGetLastError();
 }
 

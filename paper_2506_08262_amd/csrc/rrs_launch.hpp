@@ -24,6 +24,8 @@ struct GenArgs {
     uint64_t seed, qbase;
     const double *pole;
     double *UT;
+    int32_t first_cap = 0;  // 1: refinement 1 draws from Alg. S4's cap (phi = 1) too
+    int32_t area_cap = 0;   // 1: cap directions uniform in area instead of in angle
 };
 
 struct ProjArgs {
@@ -137,10 +139,10 @@ struct SignArgs {
     const float *cmarg;        // [npad]
     int64_t npad, m, ldm, qb;
     uint32_t *cnt;             // [qb][ldm][2]
-    uint64_t *queue;
-    uint32_t *qcount;
+    uint64_t *queue;           // qcap words: recheck entries
+    uint32_t *qcount;          // zeroed by the caller; kSignQueueOverflow on overflow
     uint64_t qcap;
-    const double *UT;          // [qb][d][ldm] binary64 directions (cull bounds)
+    const double *UT;          // [qb][d][ldm] binary64 directions (cull bounds, recheck)
     const double *Z;           // [qb][d]
     // list mode: the undecided points of each query (null: every point)
     const uint32_t *lists, *lcount, *offs;
@@ -160,15 +162,24 @@ struct CullArgs {
     unsigned long long *pairs; // optional: adds sum_q lcount_q * m (pairs the GEMM evaluates)
 };
 bool sign_supported(int prec, int64_t d);
+// A queue segment of the sign GEMM that overflowed sets this bit of *qcount
+// (the queue's words are split into one segment per wave of its grid).
+constexpr uint32_t kSignQueueOverflow = 0x80000000u;
 // Sign counts (cnt must hold the starting counts) and the recheck queue.
 hipError_t launch_sign(const SignArgs &a, hipStream_t st);
-// Binary64 recount of the (query, direction, 64-row tile) blocks the sign
-// GEMM queued; adds both counts of every live row.
-hipError_t launch_block_recheck(const SignArgs &a, const double *XT, int64_t ldx,
-                                uint64_t *tally, hipStream_t st);
+// Binary64 recount of the (query, direction, half tile of 32 rows) blocks
+// the sign GEMM queued; adds both counts of every live row.  X: [n][d].
+hipError_t launch_block_recheck(const SignArgs &a, const double *X, uint64_t *tally,
+                                hipStream_t st);
 // Culls the points of every query against its cap: lists, item offsets, and
 // cnt set to the decided points' counts.
 hipError_t launch_cull(const SignArgs &a, const CullArgs &c, hipStream_t st);
+// Mahalanobis depth D_M(L) (rrs_maha.hip): workspace bytes and the enqueue
+// of the whole computation; *flag_out (device word) is 1 afterwards when the
+// covariance was not positive definite.
+size_t maha_ws_bytes(int64_t n, int64_t d, int64_t m);
+hipError_t maha_enqueue(const double *X, int64_t n, int64_t d, const double *Z, int64_t m,
+                        double *depth, void *ws, uint32_t **flag_out, hipStream_t st);
 hipError_t launch_init_state(int64_t qb, int64_t d, int64_t n, double *pole, double *best_d,
                              int64_t *best_c, hipStream_t st);
 hipError_t launch_finalize(int64_t qb, int64_t d, int64_t n, bool half, const double *pole,

@@ -34,6 +34,8 @@
 #include <math.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 #include "rrs_device.hpp"
 #include "rrs_launch.hpp"
 #include "rrs_select_common.hpp"
@@ -81,6 +83,7 @@ struct WaveG {
 template <int CAP, int STG>
 struct alignas(16) RcShared {
     static constexpr int kCap = CAP, kStage = STG;
+    static constexpr bool kShared = false;  // no second histogram / candidate list
     uint32_t hist[kHistN];
     uint32_t skey[64];
     uint32_t srank[64];
@@ -98,6 +101,16 @@ struct alignas(16) RcShared {
     uint64_t rresult, minkey;
     double zs[kDs], us[kDs];   // the column's query and direction (d <= kDs)
     double xs[STG];            // the candidates' data rows, gathered in one round
+};
+
+// Streamed columns: a second histogram and candidate list, so that two order
+// statistics of one column share their passes over it.
+template <int CAP, int STG>
+struct alignas(16) RcSharedS : RcShared<CAP, STG> {
+    static constexpr bool kShared = true;
+    uint32_t hist2[kHistN];
+    uint32_t cidx2[CAP];
+    uint32_t ncand2, nlow2;
 };
 
 // One column and what its exact recomputation needs.
@@ -787,6 +800,369 @@ __device__ __forceinline__ bool rc_select(const Col &C, const SRC &src, double m
     return false;
 }
 
+
+// ---------------------------------------------------------------------------
+// Shared passes for streamed columns (n > 16384, reread from HBM by every
+// pass).  Asymmetric projection depth: one pass bins the brackets of both the
+// median and the MAD_+ rank, one pass collects both windows' candidates; the
+// MAD_+ rank is that of the tie-free count #{t <= med} (ceil(n / 2)), which
+// the median's window then confirms.  Projection depth: the MAD's histogram is
+// built in the median's window pass, binning |s - m~| around the centre m~ of
+// the median's window instead of the exact median; the rank statistic moves
+// by at most |m~ - med|, which widens the MAD's window.  Whatever these cannot
+// serve (a bracket that misses, target bins that hold too many values for one
+// window, ties at the median) is left to the separate selects.
+// ---------------------------------------------------------------------------
+struct Target {
+    float scale, off;    // linear bins of the bracket
+    uint32_t bA, bB;     // bins holding ranks k, k + 1
+    uint32_t beforeA;    // values below bin A (the below slots included)
+    float midf, hwf;     // window |x - mid| <= hw in binary32
+};
+
+// The 64 sampled approximations of phase PH (relative to sigf), their keys
+// and ranks in LDS.
+template <int PH, class G, class SRC, class SH>
+__device__ __forceinline__ void take_samples(const SRC &src, float sigf, SH &sh)
+{
+    const int tid = G::tid(), lane = tid & 63, wave = tid >> 6;
+    constexpr int kPer = 64 / G::kWaves;
+    if (tid < 64) sh.srank[tid] = 0;
+    if (lane < kPer) {
+        const int slot = wave * kPer + lane;
+        const float x = approx_v<PH>(src.sample(slot), sigf);
+        const uint32_t kx = fkey32<PH>(x);
+        sh.skey[slot] = fkey_finite<PH>(kx) ? kx : 0xFFFFFFFFu;
+        sh.sval[slot] = x;
+    }
+    G::sync();
+    {
+        const uint32_t mine = sh.skey[lane];
+        uint32_t part = 0;
+#pragma unroll
+        for (int jj = 0; jj < kPer; ++jj) {
+            const int o = wave * kPer + jj;
+            const uint32_t ko = sh.skey[o];
+            part += (ko < mine || (ko == mine && o < lane)) ? 1u : 0u;
+        }
+        atomicAdd(&sh.srank[lane], part);
+    }
+    G::sync();
+}
+
+// Linear bins over the sampled bracket of rank k (pair: k and k + 1); false
+// when fewer than 16 samples are finite.  Every wave derives it (same values).
+template <class SH>
+__device__ __forceinline__ bool sample_bracket(const SH &sh, int64_t n, uint64_t k, bool pair,
+                                               float &scale, float &off)
+{
+    const int lane = threadIdx.x & 63;
+    const uint32_t kx = sh.skey[lane];
+    const bool ok = kx != 0xFFFFFFFFu;
+    const uint32_t rank = sh.srank[lane];
+    const uint32_t S = (uint32_t)__popcll(__ballot(ok));
+    if (S < 16) return false;
+    const double f = ((double)k + 0.5) / (double)n;
+    const double pos = f * (double)S;
+    const double del = 2.5 * sqrt((double)S * f * (1.0 - f)) + 1.5;
+    double lo = floor(pos - del), hi = ceil(pos + del + (pair ? 1.0 : 0.0));
+    if (lo < 0.0) lo = 0.0;
+    if (hi > (double)(S - 1)) hi = (double)(S - 1);
+    const uint32_t rlo = (uint32_t)lo, rhi = (uint32_t)hi;
+    const uint64_t mlo = __ballot(ok && rank == rlo), mhi = __ballot(ok && rank == rhi);
+    const float xv = sh.sval[lane];
+    const float L = lane_bcast_f(xv, __ffsll((long long)mlo) - 1);
+    const float H = lane_bcast_f(xv, __ffsll((long long)mhi) - 1);
+    lin_fit(L, H, scale, off);
+    return true;
+}
+
+// Bins of ranks k (and k + 1) in a filled histogram; false when the bracket
+// missed them or when they hold more than half the candidate room.
+template <class SH>
+__device__ __forceinline__ bool hist_target(const uint32_t *hist, uint64_t k, bool pair,
+                                            Target &t)
+{
+    const int lane = threadIdx.x & 63;
+    const uint32_t *bins = hist + kHistLo;
+    uint32_t lo = hist[lane];  // the below slots
+    for (int o = 32; o > 0; o >>= 1) lo += (uint32_t)__shfl_xor((int)lo, o);
+    uint32_t xA, rA, cA, xB, rB, cB;
+    bool fA, fB;
+    scan_hist(bins, lo, k, xA, rA, cA, fA);
+    scan_hist(bins, lo, k + 1, xB, rB, cB, fB);
+    const uint64_t ma = __ballot(fA), mb = __ballot(fB);
+    if (ma == 0 || (pair && mb == 0)) return false;
+    const int la = __ffsll((long long)ma) - 1;
+    t.bA = (uint32_t)__builtin_amdgcn_readlane((int)xA, la);
+    t.beforeA = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(k - rA), la);
+    t.bB = pair ? (uint32_t)__builtin_amdgcn_readlane((int)xB, __ffsll((long long)mb) - 1) : t.bA;
+    uint32_t held = 0;
+    for (uint32_t x = t.bA; x <= t.bB; ++x) held += bins[x];
+    return held <= (uint32_t)SH::kCap / 2;
+}
+
+// Window of the target bins with error bound Ew (already including every
+// rounding of the approximations).
+__device__ __forceinline__ void target_window(Target &t, double Ew)
+{
+    const double vlo = lin_lo(t.bA, t.scale, t.off), vhi = lin_hi(t.bB, t.scale, t.off);
+    const double wlo = vlo - 2.0 * Ew, whi = vhi + 2.0 * Ew;
+    const double mid = 0.5 * (wlo + whi);
+    t.midf = (float)mid;
+    const double hw = fmax(mid - wlo, whi - mid) * (1.0 + 0x1p-50);
+    t.hwf = __double2float_ru((hw + fabs(mid - (double)t.midf)) * (1.0 + 0x1p-50));
+}
+
+// Exact values of the nc candidates listed in idx (phase PH), into sh.cval,
+// and ranks rA (and rA + 1) among them.
+template <int PH, bool EXACT, class G, class SH>
+__device__ __forceinline__ void rank_candidates(const Col &C, const uint32_t *idx, uint32_t nc,
+                                                double med, uint64_t rA, bool pair, SH &sh,
+                                                double &a, double &b)
+{
+    constexpr uint32_t kCap = (uint32_t)SH::kCap;
+    constexpr uint32_t kQuadG = kQuad < SH::kCap / 2 ? kQuad : SH::kCap / 2;
+    const int tid = G::tid();
+    for (uint32_t p = tid; p < nc; p += G::kN)
+        sh.cval[p] = exact_v<PH>(exact_t<EXACT>(C, (int64_t)idx[p]), med);
+    G::sync();
+    const uint64_t rB = rA + 1;
+    if (nc <= kQuadG) {
+        // all-pairs ranking; the counts go to cidx[p] (below) and
+        // cidx[kCap / 2 + p] (at most) -- the lists are no longer needed
+        for (uint32_t p = tid; p < nc; p += G::kN) {
+            sh.cidx[p] = 0u;
+            sh.cidx[kCap / 2 + p] = 0u;
+        }
+        G::sync();
+        const uint32_t grp = nc >= (uint32_t)G::kN ? 1u : (uint32_t)G::kN / nc;
+        const uint32_t span = (nc + grp - 1) / grp;
+        for (uint32_t w = tid; w < nc * grp; w += G::kN) {
+            const uint32_t g = w / nc, p = w - g * nc;
+            const double mine = sh.cval[p];
+            const uint32_t x0 = g * span, x1 = x0 + span < nc ? x0 + span : nc;
+            uint32_t lt = 0, le = 0;
+            for (uint32_t x = x0; x < x1; ++x) {
+                const double o = sh.cval[x];
+                lt += (o < mine);
+                le += (o <= mine);
+            }
+            if (lt) atomicAdd(&sh.cidx[p], lt);
+            if (le) atomicAdd(&sh.cidx[kCap / 2 + p], le);
+        }
+        G::sync();
+        for (uint32_t p = tid; p < nc; p += G::kN) {
+            const uint32_t lt = sh.cidx[p], le = sh.cidx[kCap / 2 + p];
+            if (lt <= rA && rA < le) sh.resA = sh.cval[p];
+            if (pair && lt <= rB && rB < le) sh.resB = sh.cval[p];
+        }
+        G::sync();
+        a = sh.resA;
+        b = pair ? sh.resB : a;
+        G::sync();
+    } else {
+        lds_rank_pair<G>(sh, nc, rA, pair);
+        a = sh.resA;
+        b = sh.resB;
+    }
+}
+
+// Asymmetric projection depth of a streamed column with shared passes.
+// Returns 2 with D when they served the whole column, 1 with the exact
+// median and #{t <= med} when only the median's part served (ties at the
+// median, or MAD_+'s window missed), 0 when nothing was decided.
+template <bool EXACT, class G, class SH>
+__device__ __forceinline__ int rc_apd_shared(const Col &C, const StreamSrc<G> &src, SH &sh, double &D,
+                             double &med_out, uint64_t &nle_out)
+{
+    const int tid = G::tid();
+    constexpr uint32_t kCap = (uint32_t)SH::kCap;
+    const int64_t n = C.n;
+    if (!C.sane) return 0;
+    const bool odd = (n & 1) != 0;
+    const uint64_t k = odd ? (uint64_t)n / 2 : (uint64_t)n / 2 - 1;
+    // MAD_+'s rank when no other point equals the median
+    const uint64_t nle_g = odd ? k + 1 : (uint64_t)n / 2;
+    const uint64_t npos_g = (uint64_t)n - nle_g;
+    if (npos_g < 2) return 0;
+    const bool podd = (npos_g & 1) != 0;
+    const uint64_t kp = nle_g + (podd ? npos_g / 2 : npos_g / 2 - 1);
+    for (int x = tid; x < kHistN; x += G::kN) {
+        sh.hist[x] = 0;
+        sh.hist2[x] = 0;
+    }
+    if (tid == 0) {
+        sh.ncand = sh.nlow = sh.ncand2 = sh.nlow2 = 0;
+    }
+    take_samples<0, G>(src, 0.0f, sh);
+    Target t1, t2;
+    if (!sample_bracket(sh, n, k, !odd, t1.scale, t1.off)) return 0;
+    if (!sample_bracket(sh, n, kp, !podd, t2.scale, t2.off)) return 0;
+    // pass 1: both histograms
+    {
+        const int lane = tid & 63;
+        const float lo_l = -(float)(lane + 1), hi_l = (float)(kBins + lane);
+        uint32_t *const b1 = sh.hist + kHistLo;
+        uint32_t *const b2 = sh.hist2 + kHistLo;
+        src.each([&](int, float sv) {
+            atomicAdd(&b1[lin_slot(sv, t1.scale, t1.off, lo_l, hi_l)], 1u);
+            atomicAdd(&b2[lin_slot(sv, t2.scale, t2.off, lo_l, hi_l)], 1u);
+        });
+    }
+    G::sync();
+    const bool ok1 = hist_target<SH>(sh.hist, k, !odd, t1);
+    const bool ok2 = hist_target<SH>(sh.hist2, kp, !podd, t2);
+    if (!ok1 || !ok2) return 0;
+    target_window(t1, C.E);
+    target_window(t2, C.E);
+    // pass 2: both windows' candidates
+    {
+        const float fA1 = (float)t1.bA, fA2 = (float)t2.bA;
+        src.each([&](int i, float x) {
+            if (fabsf(x - t1.midf) <= t1.hwf) {
+                if (fmaf(x, t1.scale, t1.off) < fA1) atomicAdd(&sh.nlow, 1u);
+                const uint32_t p = atomicAdd(&sh.ncand, 1u);
+                if (p < kCap) sh.cidx[p] = (uint32_t)i;
+            }
+            if (fabsf(x - t2.midf) <= t2.hwf) {
+                if (fmaf(x, t2.scale, t2.off) < fA2) atomicAdd(&sh.nlow2, 1u);
+                const uint32_t p = atomicAdd(&sh.ncand2, 1u);
+                if (p < kCap) sh.cidx2[p] = (uint32_t)i;
+            }
+        });
+    }
+    G::sync();
+    const uint32_t nc1 = sh.ncand, nc2 = sh.ncand2;
+    const uint64_t B1 = (uint64_t)t1.beforeA - sh.nlow, B2 = (uint64_t)t2.beforeA - sh.nlow2;
+    G::sync();
+    if (!(nc1 <= kCap && B1 <= k && k + (odd ? 0 : 1) < B1 + nc1)) return 0;
+    double a, b;
+    rank_candidates<0, EXACT, G>(C, sh.cidx, nc1, 0.0, k - B1, !odd, sh, a, b);
+    const double med = odd ? a : (a + b) * 0.5;
+    // #{t <= med}: the points below the window and the window's candidates
+    if (tid == 0) sh.count = 0;
+    G::sync();
+    {
+        uint32_t c = 0;
+        for (uint32_t p = tid; p < nc1; p += G::kN) c += sh.cval[p] <= med ? 1u : 0u;
+        for (int o = 32; o > 0; o >>= 1) c += (uint32_t)__shfl_xor((int)c, o);
+        if ((tid & 63) == 0 && c) atomicAdd(&sh.count, c);
+    }
+    G::sync();
+    const uint64_t nle = B1 + sh.count;
+    G::sync();
+    med_out = med;
+    nle_out = nle;
+    if (nle != nle_g || !(nc2 <= kCap && B2 <= kp && kp + (podd ? 0 : 1) < B2 + nc2)) return 1;
+    double p1, p2;
+    rank_candidates<0, EXACT, G>(C, sh.cidx2, nc2, 0.0, kp - B2, !podd, sh, p1, p2);
+    const double madp = podd ? (p1 - med) : ((p1 - med) + (p2 - med)) * 0.5;
+    const double num = (med < 0.0) ? -med : 0.0;
+    D = 1.0 / (1.0 + num / madp);
+    return 2;
+}
+
+// Projection depth of a streamed column: median histogram, then the median's
+// window pass also bins the MAD's approximations, then the MAD's window.
+// Returns 2 with D when this served the whole column, 1 with the exact
+// median when only the median's part served, 0 when nothing was decided.
+template <bool EXACT, class G, class SH>
+__device__ __forceinline__ int rc_proj_shared(const Col &C, const StreamSrc<G> &src, SH &sh, double &D,
+                              double &med_out)
+{
+    const int tid = G::tid();
+    constexpr uint32_t kCap = (uint32_t)SH::kCap;
+    const int64_t n = C.n;
+    if (!C.sane) return 0;
+    const bool odd = (n & 1) != 0;
+    const uint64_t k = odd ? (uint64_t)n / 2 : (uint64_t)n / 2 - 1;
+    for (int x = tid; x < kHistN; x += G::kN) {
+        sh.hist[x] = 0;
+        sh.hist2[x] = 0;
+    }
+    if (tid == 0) {
+        sh.ncand = sh.nlow = sh.ncand2 = sh.nlow2 = 0;
+    }
+    take_samples<0, G>(src, 0.0f, sh);
+    Target t1, t2;
+    if (!sample_bracket(sh, n, k, !odd, t1.scale, t1.off)) return 0;
+    const int lane = tid & 63;
+    const float lo_l = -(float)(lane + 1), hi_l = (float)(kBins + lane);
+    {
+        uint32_t *const b1 = sh.hist + kHistLo;
+        src.each([&](int, float sv) {
+            atomicAdd(&b1[lin_slot(sv, t1.scale, t1.off, lo_l, hi_l)], 1u);
+        });
+    }
+    G::sync();
+    if (!hist_target<SH>(sh.hist, k, !odd, t1)) return 0;
+    target_window(t1, C.E);
+    // the median (shifted by c) lies in [vlo - E, vhi + E]; its centre m~ is
+    // within dm of it
+    const double vlo = lin_lo(t1.bA, t1.scale, t1.off), vhi = lin_hi(t1.bB, t1.scale, t1.off);
+    const double mt = 0.5 * (vlo + vhi);
+    const float mtf = (float)mt;
+    const double dm = 0.5 * (vhi - vlo) + C.E + fabs(mt - (double)mtf);
+    // the MAD's bracket from the samples' deviations from m~ (binary32)
+    take_samples<1, G>(src, mtf, sh);
+    const bool ok2 = sample_bracket(sh, n, k, !odd, t2.scale, t2.off);
+    // pass 2: the median's candidates and the MAD's histogram of |s - m~|
+    {
+        const float fA1 = (float)t1.bA;
+        uint32_t *const b2 = sh.hist2 + kHistLo;
+        src.each([&](int i, float x) {
+            if (fabsf(x - t1.midf) <= t1.hwf) {
+                if (fmaf(x, t1.scale, t1.off) < fA1) atomicAdd(&sh.nlow, 1u);
+                const uint32_t p = atomicAdd(&sh.ncand, 1u);
+                if (p < kCap) sh.cidx[p] = (uint32_t)i;
+            }
+            if (ok2) atomicAdd(&b2[lin_slot(fabsf(x - mtf), t2.scale, t2.off, lo_l, hi_l)], 1u);
+        });
+    }
+    G::sync();
+    const uint32_t nc1 = sh.ncand;
+    const uint64_t B1 = (uint64_t)t1.beforeA - sh.nlow;
+    G::sync();
+    if (!(nc1 <= kCap && B1 <= k && k + (odd ? 0 : 1) < B1 + nc1)) return 0;
+    double a, b;
+    rank_candidates<0, EXACT, G>(C, sh.cidx, nc1, 0.0, k - B1, !odd, sh, a, b);
+    const double med = odd ? a : (a + b) * 0.5;
+    med_out = med;
+    if (!ok2 || !hist_target<SH>(sh.hist2, k, !odd, t2)) return 1;
+    // |s - m~| in binary32 is within E + dm of |t - med|, plus the roundings
+    // of the difference
+    const double vlo2 = lin_lo(t2.bA, t2.scale, t2.off), vhi2 = lin_hi(t2.bB, t2.scale, t2.off);
+    const double Ew = (C.E + dm) * 1.000001 +
+                      0x1p-22 * (fabs(mt) + fabs(vlo2) + fabs(vhi2) + C.E + dm) + 1e-300;
+    target_window(t2, Ew);
+    // pass 3: the MAD's candidates
+    {
+        const float fA2 = (float)t2.bA;
+        src.each([&](int i, float sv) {
+            const float x = fabsf(sv - mtf);
+            if (fabsf(x - t2.midf) <= t2.hwf) {
+                if (fmaf(x, t2.scale, t2.off) < fA2) atomicAdd(&sh.nlow2, 1u);
+                const uint32_t p = atomicAdd(&sh.ncand2, 1u);
+                if (p < kCap) sh.cidx2[p] = (uint32_t)i;
+            }
+        });
+    }
+    G::sync();
+    const uint32_t nc2 = sh.ncand2;
+    const uint64_t B2 = (uint64_t)t2.beforeA - sh.nlow2;
+    G::sync();
+    if (!(nc2 <= kCap && B2 <= k && k + (odd ? 0 : 1) < B2 + nc2)) return 1;
+    double m1, m2;
+    rank_candidates<1, EXACT, G>(C, sh.cidx2, nc2, med, k - B2, !odd, sh, m1, m2);
+    const double mad = odd ? m1 : (m1 + m2) * 0.5;
+    if (mad == 0.0)
+        D = (med == 0.0) ? 1.0 : 0.0;
+    else
+        D = 1.0 / (1.0 + fabs(med) / mad);
+    return 2;
+}
+
 // Number of points with t <= med: from the median's window when it served,
 // else by a counting pass over recomputed values.
 template <bool EXACT, class G, class SH>
@@ -821,11 +1197,26 @@ __device__ __forceinline__ double rc_depth(const Col &C, const SRC &src, SH &sh,
     const int64_t n = C.n;
     const bool odd = (n & 1) != 0;
     const uint64_t k = odd ? (uint64_t)n / 2 : (uint64_t)n / 2 - 1;
-    double a, b;
+    double med = 0.0;
+    bool have_med = false;
+    uint64_t nle_sh = 0;
+    if constexpr (SRC::kMaxLevel > 0 && SH::kShared) {
+        // streamed column: the order statistics share passes
+        double D;
+        const int st = NOTION == NOTION_APD
+                           ? rc_apd_shared<EXACT, G>(C, src, sh, D, med, nle_sh)
+                           : rc_proj_shared<EXACT, G>(C, src, sh, D, med);
+        if (st == 2) return D;
+        have_med = st == 1;
+        G::sync();
+    }
+    bool win = false;
     uint64_t below = 0;
-    const bool win =
-        rc_select<0, EXACT, G>(C, src, 0.0, 0.0, C.E, k, !odd, a, b, &below, sh, stats);
-    const double med = odd ? a : (a + b) * 0.5;
+    if (!have_med) {
+        double a, b;
+        win = rc_select<0, EXACT, G>(C, src, 0.0, 0.0, C.E, k, !odd, a, b, &below, sh, stats);
+        med = odd ? a : (a + b) * 0.5;
+    }
     if (NOTION == NOTION_PROJECTION) {
         double m1, m2;
         uint64_t b1 = 0;
@@ -834,7 +1225,7 @@ __device__ __forceinline__ double rc_depth(const Col &C, const SRC &src, SH &sh,
         if (mad == 0.0) return (med == 0.0) ? 1.0 : 0.0;
         return 1.0 / (1.0 + fabs(med) / mad);
     }
-    const uint64_t nle = rc_count_le<EXACT, G>(C, med, win, below, sh);
+    const uint64_t nle = have_med ? nle_sh : rc_count_le<EXACT, G>(C, med, win, below, sh);
     const uint64_t npos = (uint64_t)n - nle;
     const double num = (med < 0.0) ? -med : 0.0;
     if (npos == 0) return (num == 0.0) ? 1.0 : 0.0;
@@ -850,7 +1241,7 @@ __device__ __forceinline__ double rc_depth(const Col &C, const SRC &src, SH &sh,
 // One column per group G (a workgroup of two or four waves, or a 64-thread
 // workgroup of one wave).  VPT > 0: the column in registers (n <= G::kN VPT); VPT == 0:
 // streamed.
-template <int NOTION, bool EXACT, int VPT, class G, int CAP, int STG>
+template <int NOTION, bool EXACT, int VPT, class G, class SH>
 __device__ __forceinline__ void select_column(const float *__restrict__ S, int64_t n, int64_t m,
                                               int64_t ldm, const double *__restrict__ cq,
                                               const double *__restrict__ eq,
@@ -858,7 +1249,7 @@ __device__ __forceinline__ void select_column(const float *__restrict__ S, int64
                                               const double *__restrict__ Zb,
                                               const double *__restrict__ UT,
                                               double *__restrict__ Dj, uint32_t *__restrict__ stats,
-                                              RcShared<CAP, STG> &sh)
+                                              SH &sh)
 {
     const int tid = G::tid();
     const int64_t j = blockIdx.x;
@@ -918,9 +1309,10 @@ __global__ __launch_bounds__(G::kN) void k_select_rc(const float *__restrict__ S
                                                      double *__restrict__ Dj,
                                                      uint32_t *__restrict__ stats)
 {
-    __shared__ RcShared<CAP, STG> sh;
-    select_column<NOTION, EXACT, VPT, G, CAP, STG>(S, n, m, ldm, cq, eq, X, d, Zb, UT, Dj, stats,
-                                                   sh);
+    // streamed columns (VPT == 0) carry the second histogram and list
+    using SH = typename std::conditional<VPT == 0, RcSharedS<CAP, STG>, RcShared<CAP, STG>>::type;
+    __shared__ SH sh;
+    select_column<NOTION, EXACT, VPT, G, SH>(S, n, m, ldm, cq, eq, X, d, Zb, UT, Dj, stats, sh);
 }
 
 template <int NOTION, bool EXACT, int VPT, class G, int CAP, int STG>

@@ -6,7 +6,8 @@
 // the direction operands carrying the query's centring term in two extra K
 // columns, three bf16 products per K step (A_hi B_hi + A_hi B_lo + A_lo B_hi)
 // accumulated in binary32; a sign is taken from t^ only outside a rigorous
-// margin and the pair is queued for the binary64 recheck otherwise.  Here the
+// margin, and the rows inside it are queued, as a row mask per half column of
+// a wave tile, for the binary64 recheck.  Here the
 // kernel is persistent: a fixed grid (two workgroups per CU) walks a list of
 // items, each item one tile of 128 directions kept in LDS for up to `rpi`
 // tiles of 256 points, with the per-column counts held in registers across
@@ -43,8 +44,8 @@ constexpr int kTN = 128;  // directions per item
 
 // LDS of one workgroup: the item's direction operands (hi, lo) with rows
 // padded by 16 bytes (row pitch 2 KS + 1 pieces of 16 bytes: the 8 lanes of
-// one ds_read_b128 phase hit distinct bank groups), count reduction, and the
-// point indices of the current point tile.
+// one ds_read_b128 phase hit distinct bank groups), count reduction, and, for
+// the cull epilogue, the norms of each wave tile's rows and the list positions.
 template <int KS>
 struct alignas(16) SignLds {
     bf16x8 b[2][kTN][2 * KS + 1];
@@ -65,11 +66,14 @@ struct SignParams {
     int32_t m, ldm, qb;        // directions per query, count stride, queries
     float kappa_a;             // data part of the margin (times |a_i|)
     int32_t rpi;               // point tiles per item
-    // sign epilogue
+    // sign epilogue: counts, and per wave of the grid a queue segment of
+    // `seg` entries (two words each) with its fill in segcnt; a segment that
+    // overflows sets bit 31 of *qflag
     uint32_t *cnt;             // [qb][ldm][2]
     uint64_t *queue;
-    uint32_t *qcount;
-    uint64_t qcap;
+    uint32_t *segcnt;
+    uint32_t *qflag;
+    uint32_t seg;
     // list mode (sign GEMM after culling); lists == nullptr: all points
     const uint32_t *lists;     // [qb][n] undecided points per query
     const uint32_t *lcount;    // [qb]
@@ -215,11 +219,55 @@ __device__ __forceinline__ int acc_row(int rt, int r, int lh)
     return rt * 32 + (r >> 2) * 8 + lh * 4 + (r & 3);
 }
 
+// Bits of `b` set below this lane.
+__device__ __forceinline__ uint32_t lane_rank(uint64_t b)
+{
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(b >> 32),
+                                     __builtin_amdgcn_mbcnt_lo((uint32_t)b, 0u));
+}
+
 __device__ __forceinline__ float wave_max(float v)
 {
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) v = fmaxf(v, __shfl_xor(v, off));
     return v;
+}
+
+// Signs of one wave tile against the margin M[ct] of this lane's columns, as
+// bit masks over the lane half's 32 rows (bit 16 rt + r): rows with t^ above
+// the margin (above) and rows with |t^| above it (sure).  The tests take sign
+// bits of differences (M - v < 0 exactly when v > M: a difference of two
+// binary32 values is zero only when they are equal), so they stay in vector
+// registers; a NaN, were there one, would not read as sure.
+__device__ __forceinline__ void tile_signs(const f32x16 (&acc)[2][4], const float (&M)[4],
+                                           uint32_t (&above)[4], uint32_t (&sure)[4])
+{
+#pragma unroll
+    for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            const int k = rt * 16 + r;
+#pragma unroll
+            for (int ct = 0; ct < 4; ++ct) {
+                const float v = acc[rt][ct][r];
+                above[ct] |= (__float_as_uint(M[ct] - v) >> 31) << k;
+                sure[ct] |= (__float_as_uint(M[ct] - fabsf(v)) >> 31) << k;
+            }
+            __builtin_amdgcn_sched_barrier(0);  // a row at a time: bounded live ranges
+        }
+}
+
+// Rows of the wave tile that lane half lh holds (bit 16 rt + r) below wl.
+__device__ __forceinline__ uint32_t live_rows(int wl, int lh)
+{
+    if (wl >= 64) return 0xFFFFFFFFu;
+    uint32_t m = 0u;
+#pragma unroll
+    for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+        for (int r = 0; r < 16; ++r)
+            if (acc_row(rt, r, lh) < wl) m |= 1u << (rt * 16 + r);
+    return m;
 }
 
 // ---------------------------------------------------------------------------
@@ -245,6 +293,9 @@ __global__ __launch_bounds__(256, 2) void k_sign(SignParams P)
     const int32_t total = list ? (int32_t)P.offs[P.qb]
                                : ((P.n + rows_per_item - 1) / rows_per_item) * nct_all;
     const Sched sc = schedule(total);
+    const uint32_t gw = blockIdx.x * 4u + (uint32_t)wave;  // this wave's queue segment
+    uint64_t *const myq = P.queue + 2ull * (uint64_t)gw * (uint64_t)P.seg;
+    uint32_t nq = 0;
     for (int32_t it = sc.lo; it < sc.hi; it += sc.step) {
         int32_t J0, jend, rbeg, rend;
         Rsrc LS = rsrc(nullptr, 0u);
@@ -268,13 +319,13 @@ __global__ __launch_bounds__(256, 2) void k_sign(SignParams P)
         }
         __syncthreads();  // the previous item's reads of L are done
         stage_b<KS>(B0, B1, (uint32_t)J0, L);
+        // column part of the margin; -inf for columns past jend, which then
+        // never look uncertain (their counts are dropped at the end)
         float cm[4];
-        bool jl[4];
 #pragma unroll
         for (int ct = 0; ct < 4; ++ct) {
             const int32_t J = J0 + ct * 32 + lr;
-            jl[ct] = J < jend;
-            cm[ct] = jl[ct] ? ld_f32(CM, (uint32_t)J * 4u) : 0.0f;
+            cm[ct] = J < jend ? ld_f32(CM, (uint32_t)J * 4u) : -INFINITY;
         }
         __syncthreads();
         uint32_t pos[4] = {0u, 0u, 0u, 0u}, neg[4] = {0u, 0u, 0u, 0u};
@@ -299,47 +350,43 @@ __global__ __launch_bounds__(256, 2) void k_sign(SignParams P)
             float M[4];
 #pragma unroll
             for (int ct = 0; ct < 4; ++ct) M[ct] = fmaf(P.kappa_a, amax, cm[ct]);
-            uint32_t tp[4] = {0u, 0u, 0u, 0u}, tn[4] = {0u, 0u, 0u, 0u};
-            int lrows = 0;
+            uint32_t above[4] = {0u, 0u, 0u, 0u}, um[4] = {0u, 0u, 0u, 0u};
+            tile_signs(acc, M, above, um);
+            {
+                const uint32_t live = live_rows(wl, lh);
 #pragma unroll
-            for (int rt = 0; rt < 2; ++rt)
-#pragma unroll
-                for (int r = 0; r < 16; ++r) {
-                    const bool rl = acc_row(rt, r, lh) < wl;
-                    lrows += rl ? 1 : 0;
-#pragma unroll
-                    for (int ct = 0; ct < 4; ++ct) {
-                        const float v = acc[rt][ct][r];
-                        tp[ct] += (rl && v > M[ct]) ? 1u : 0u;
-                        tn[ct] += (rl && v < -M[ct]) ? 1u : 0u;
-                    }
-                }
-            // a column of the wave tile with an uncertain sign (rare) keeps no
-            // count from this tile: its live rows are recomputed in binary64
-            // by the block recheck, which counts both sides for all of them
-#pragma unroll
-            for (int ct = 0; ct < 4; ++ct) {
-                int bad = (jl[ct] && tp[ct] + tn[ct] < (uint32_t)lrows) ? 1 : 0;
-                bad |= __shfl_xor(bad, 32);
-                if (bad) {
-                    if (lh == 0) {
-                        const int32_t J = J0 + ct * 32 + lr;
-                        const int32_t qi = J / P.m, j = J - qi * P.m;
-                        const uint32_t slot = atomicAdd(P.qcount, 1u);
-                        if ((uint64_t)slot < P.qcap)
-                            P.queue[slot] = ((uint64_t)qi << 48) | ((uint64_t)j << 32) |
-                                            (uint64_t)(uint32_t)r0;
-                    }
-                } else {
-                    pos[ct] += tp[ct];
-                    neg[ct] += tn[ct];
+                for (int ct = 0; ct < 4; ++ct) {
+                    const uint32_t sure = um[ct] & live;
+                    above[ct] &= live;
+                    pos[ct] += (uint32_t)__builtin_popcount(above[ct]);
+                    neg[ct] += (uint32_t)__builtin_popcount(sure & ~above[ct]);
+                    um[ct] = live & ~um[ct];  // uncertain rows
                 }
             }
+            // half columns with uncertain rows (rare): one entry each,
+            // appended to this wave's queue segment
+            uint32_t off = nq;
+#pragma unroll
+            for (int ct = 0; ct < 4; ++ct) {
+                const uint64_t bal = __builtin_amdgcn_ballot_w64(um[ct] != 0u);
+                const uint32_t slot = off + lane_rank(bal);
+                if (um[ct] != 0u && slot < P.seg) {
+                    const int32_t J = J0 + ct * 32 + lr;
+                    const int32_t qi = J / P.m, j = J - qi * P.m;
+                    uint64_t *e = myq + 2 * (uint64_t)slot;
+                    e[0] = ((uint64_t)qi << 48) | ((uint64_t)j << 32) |
+                           (uint64_t)((uint32_t)r0 | (uint32_t)lh);
+                    e[1] = (uint64_t)um[ct];
+                }
+                off += (uint32_t)__builtin_popcountll(bal);
+            }
+            nq = off;
         }
         // counts of the item: lanes l and l + 32 hold the same column
 #pragma unroll
         for (int ct = 0; ct < 4; ++ct) {
-            uint32_t pc = jl[ct] ? pos[ct] : 0u, nc = jl[ct] ? neg[ct] : 0u;
+            const bool jl = J0 + ct * 32 + lr < jend;
+            uint32_t pc = jl ? pos[ct] : 0u, nc = jl ? neg[ct] : 0u;
             pc += (uint32_t)__shfl_xor((int)pc, 32);
             nc += (uint32_t)__shfl_xor((int)nc, 32);
             if (lh == 0) {
@@ -358,6 +405,10 @@ __global__ __launch_bounds__(256, 2) void k_sign(SignParams P)
                 atomicAdd(&P.cnt[((size_t)qi * P.ldm + j) * 2 + w], s);
             }
         }
+    }
+    if (lane == 0) {
+        P.segcnt[gw] = nq < P.seg ? nq : P.seg;
+        if (nq > P.seg) atomicOr(P.qflag, kSignQueueOverflow);  // overflow: recount in binary64
     }
 }
 
@@ -484,45 +535,55 @@ __global__ __launch_bounds__(256, 2) void k_cull(SignParams P)
     }
 }
 
-// Block recheck: each queued (query, direction, wave tile) gets the binary64
-// recipe value of every live row of the tile (one wave, one row per lane)
-// and both counts from them.  Rows index the query's list in list mode,
-// the points otherwise.
+// Recheck of the uncertain rows: a queue entry is two words, (query,
+// direction, wave tile row r0, lane half h) and the mask of the half column's
+// uncertain rows (bit 16 rt + r: row 32 rt + 8 (r / 4) + 4 h + r % 4 of the
+// wave tile), nearly always a single row.  One lane per entry: each masked
+// row gets the binary64 recipe value (the recipe's fma chain over the point's
+// row) and both counts from it; the other rows of the half column were
+// counted by the sign GEMM.  Workgroup b takes the entries of queue segment
+// b (those of one wave of the sign GEMM, in the order it met them), so a
+// wave's lanes mostly share the query and read nearby directions.  Rows index
+// the query's list in list mode, the points otherwise.
 __global__ __launch_bounds__(256) void k_block_recheck(
-    const uint64_t *__restrict__ queue, const uint32_t *__restrict__ qcount, uint64_t qcap,
-    const double *__restrict__ XT, int64_t ldx, int64_t n, int64_t d,
-    const double *__restrict__ Zb, const double *__restrict__ UT, int64_t ldm,
-    const uint32_t *__restrict__ lists, const uint32_t *__restrict__ lcount,
+    const uint64_t *__restrict__ queue, const uint32_t *__restrict__ segcnt, uint32_t seg,
+    const double *__restrict__ X, int64_t n, int64_t d, const double *__restrict__ Zb,
+    const double *__restrict__ UT, int64_t ldm, const uint32_t *__restrict__ lists,
     uint32_t *__restrict__ cnt, unsigned long long *__restrict__ tally)
 {
-    const uint64_t total = *qcount < qcap ? *qcount : qcap;
-    const int lane = threadIdx.x & 63;
-    const uint64_t w0 = ((uint64_t)blockIdx.x * 256 + threadIdx.x) >> 6;
-    const uint64_t nw = ((uint64_t)gridDim.x * 256) >> 6;
-    for (uint64_t e = w0; e < total; e += nw) {
-        const uint64_t w = queue[e];
+    // workgroup b: the entries of queue segment b
+    const uint64_t *q = queue + 2ull * (uint64_t)blockIdx.x * (uint64_t)seg;
+    const uint32_t total = segcnt[blockIdx.x];
+    uint32_t pairs = 0;
+    for (uint32_t e = threadIdx.x; e < total; e += 256) {
+        const uint64_t w = q[2 * (uint64_t)e];
+        const uint32_t mask = (uint32_t)q[2 * (uint64_t)e + 1];
         const int64_t qi = (int64_t)(w >> 48);
         const int64_t j = (int64_t)((w >> 32) & 0xFFFF);
-        const int64_t r0 = (int64_t)(w & 0xFFFFFFFFu);
-        const int64_t lim = lists ? (int64_t)lcount[qi] : n;
-        const int64_t row = r0 + lane;
-        const bool live = row < lim;
-        int64_t i = 0;
-        if (live) i = lists ? (int64_t)lists[qi * n + row] : row;
+        const uint32_t lo = (uint32_t)(w & 0xFFFFFFFFu);
+        const int64_t r0 = (int64_t)(lo & ~63u) + 4 * (int64_t)(lo & 1u);
         const double *z = Zb + qi * d;
         const double *u = UT + qi * d * ldm + j;
-        double t = 0.0;
-        for (int64_t c = 0; c < d; ++c) t = fma(XT[c * ldx + i] - z[c], u[c * ldm], t);
-        const uint64_t le = __builtin_amdgcn_ballot_w64(live && t <= 0.0);
-        const uint64_t ge = __builtin_amdgcn_ballot_w64(live && t >= 0.0);
-        if (lane == 0) {
-            if (le) atomicAdd(&cnt[(qi * ldm + j) * 2], (uint32_t)__builtin_popcountll(le));
-            if (ge) atomicAdd(&cnt[(qi * ldm + j) * 2 + 1], (uint32_t)__builtin_popcountll(ge));
-            if (tally) {
-                const uint64_t lv = __builtin_amdgcn_ballot_w64(live);
-                atomicAdd(tally, (unsigned long long)__builtin_popcountll(lv));
-            }
+        uint32_t le = 0, ge = 0;
+        for (uint32_t bits = mask; bits; bits &= bits - 1u) {
+            const int k = __builtin_ctz(bits);
+            const int64_t row = r0 + (k >> 4) * 32 + ((k >> 2) & 3) * 8 + (k & 3);
+            const int64_t i = lists ? (int64_t)lists[qi * n + row] : row;
+            const double *x = X + i * d;
+            double t = 0.0;
+#pragma unroll 4
+            for (int64_t c = 0; c < d; ++c) t = fma(x[c] - z[c], u[c * ldm], t);
+            le += t <= 0.0 ? 1u : 0u;
+            ge += t >= 0.0 ? 1u : 0u;
         }
+        if (le) atomicAdd(&cnt[(qi * ldm + j) * 2], le);
+        if (ge) atomicAdd(&cnt[(qi * ldm + j) * 2 + 1], ge);
+        pairs += (uint32_t)__builtin_popcount(mask);
+    }
+    if (tally) {
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) pairs += (uint32_t)__shfl_xor((int)pairs, off);
+        if ((threadIdx.x & 63) == 0 && pairs) atomicAdd(tally, (unsigned long long)pairs);
     }
 }
 
@@ -643,6 +704,21 @@ int grid_size()
     return ((2 * g_cus + 7) / 8) * 8;
 }
 
+// Recheck queue of the sign GEMM (qcap words): one segment of `seg` entries
+// (two words each) per wave of the grid, then the segment fills (one word per
+// two segments) at the end.
+struct SignQueue {
+    uint32_t *segcnt;
+    uint32_t seg, nseg;
+};
+SignQueue sign_queue(const SignArgs &a, int grid)
+{
+    const uint64_t nseg = (uint64_t)grid * 4;
+    const uint64_t cw = (nseg + 1) / 2;
+    const uint64_t seg = a.qcap > cw ? (a.qcap - cw) / 2 / nseg : 0;
+    return {(uint32_t *)(a.queue + (a.qcap - cw)), (uint32_t)seg, (uint32_t)nseg};
+}
+
 #define RRS_SIGN_KS_SWITCH(KS_VAR, F, ...)                                                  \
     switch (KS_VAR) {                                                                       \
     case 1: F<1>(__VA_ARGS__); break;                                                       \
@@ -695,13 +771,15 @@ hipError_t launch_sign(const SignArgs &a, hipStream_t st)
     p.qb = (int32_t)a.qb;
     p.kappa_a = (float)((kappa + canon) * 1.000001);
     p.cnt = a.cnt;
+    const int grid = grid_size();
+    const SignQueue sq = sign_queue(a, grid);
     p.queue = a.queue;
-    p.qcount = a.qcount;
-    p.qcap = a.qcap;
+    p.segcnt = sq.segcnt;
+    p.qflag = a.qcount;
+    p.seg = sq.seg;
     p.lists = a.lists;
     p.lcount = a.lcount;
     p.offs = a.offs;
-    const int grid = grid_size();
     // point tiles per item: keep about four items per workgroup at least
     int rpi = 4;
     if (!a.lists) {
@@ -716,11 +794,12 @@ hipError_t launch_sign(const SignArgs &a, hipStream_t st)
     return hipGetLastError();
 }
 
-hipError_t launch_block_recheck(const SignArgs &a, const double *XT, int64_t ldx,
-                                uint64_t *tally, hipStream_t st)
+hipError_t launch_block_recheck(const SignArgs &a, const double *X, uint64_t *tally,
+                                hipStream_t st)
 {
-    hipLaunchKernelGGL(k_block_recheck, dim3(1024), dim3(256), 0, st, a.queue, a.qcount, a.qcap,
-                       XT, ldx, a.n, a.d, a.Z, a.UT, a.ldm, a.lists, a.lcount, a.cnt,
+    const SignQueue sq = sign_queue(a, grid_size());
+    hipLaunchKernelGGL(k_block_recheck, dim3(sq.nseg), dim3(256), 0, st, a.queue, sq.segcnt, sq.seg,
+                       X, a.n, a.d, a.Z, a.UT, a.ldm, a.lists, a.cnt,
                        (unsigned long long *)tally);
     return hipGetLastError();
 }

@@ -8,10 +8,9 @@ Sigma_ij = 2^-|i-j| (or a multivariate Student t with that scatter), depths of
 randomly chosen points of the data set computed by RRS with 40 refinements,
 100,000 directions and alpha = 0.9, then Spearman's rho and Kendall's tau of
 each depth against the true density, beside the Mahalanobis depth with the
-sample mean and the maximum-likelihood covariance.  The depths come from the
-library on the GPU; the density, the Mahalanobis depth and the correlations
-are evaluated here on the host (numpy / scipy), since they are comparators
-and not part of the hot path.
+sample mean and the maximum-likelihood covariance.  The depths, the
+Mahalanobis depth included, come from the library on the GPU; the density and
+the correlations are evaluated here on the host (scipy).
 
     python -m paper_2506_08262_amd.ranking --dims 5 10 25 50 --queries 500
 """
@@ -53,17 +52,6 @@ def true_logpdf(Z: np.ndarray, law: str = "gaussian", nu: float = 0.0) -> np.nda
     return stats.multivariate_t(loc=np.zeros(d), shape=S, df=nu).logpdf(Z)
 
 
-def mahalanobis_depth(X: np.ndarray, Z: np.ndarray) -> np.ndarray:
-    """D_M(L): (1 + (z - mu)' S^-1 (z - mu))^-1 with the sample mean and the
-    maximum-likelihood covariance (divisor n) of X."""
-    mu = X.mean(axis=0)
-    A = X - mu
-    S = A.T @ A / X.shape[0]
-    B = Z - mu
-    q = np.einsum("ij,ij->i", B, np.linalg.solve(S, B.T).T)
-    return 1.0 / (1.0 + q)
-
-
 def rank_correlations(a: np.ndarray, b: np.ndarray) -> dict:
     """Spearman's rho and Kendall's tau (tau-b) of two score vectors."""
     from scipy import stats
@@ -102,7 +90,7 @@ def study(d: int, n: int = 100_000, queries: int = 5000, K: int = 100_000, n_ref
         out[f"{notion}_seconds"] = sec
         out[f"{notion}_projections_per_s"] = queries * n_refine * m * n / sec
     logpdf = true_logpdf(Z, law, nu)
-    dm = mahalanobis_depth(X, Z)
+    dm = rrs.rrs_depth_mahalanobis(Xt, Zt).cpu().numpy()
     out["pdf_x_DP"] = rank_correlations(logpdf, depths["projection"])
     out["pdf_x_DAP"] = rank_correlations(logpdf, depths["apd"])
     out["pdf_x_DML"] = rank_correlations(logpdf, dm)

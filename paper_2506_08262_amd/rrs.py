@@ -18,6 +18,8 @@ LIB_PATH = os.path.join(HERE, "librrs.so")
 
 RRS_OK, RRS_E_INVAL, RRS_E_NOMEM, RRS_E_DEVICE = 0, 1, 2, 3
 RRS_FLAG_GRAPH = 1
+RRS_FLAG_FIRST_CAP = 2
+RRS_FLAG_AREA_CAP = 4
 RRS_E_BUSY, RRS_E_CANCELLED, RRS_E_INTERNAL = 4, 5, 6
 RRS_F64, RRS_F32_RECHECK, RRS_BF16_RECHECK, RRS_F32_PLAIN = 0, 1, 2, 3
 PRECISIONS = {"f64": RRS_F64, "f32": RRS_F32_RECHECK, "bf16": RRS_BF16_RECHECK,
@@ -30,7 +32,8 @@ EXPORTED = ["rrs_depth_halfspace", "rrs_depth_projection", "rrs_depth_apd",
             "rrs_last_error", "rrs_release_workspace", "rrs_version", "rrs_debug_directions",
             "rrs_profile_enable", "rrs_profile_read", "rrs_profile_counter",
             "rrs_ctx_create", "rrs_ctx_destroy", "rrs_dataset_put", "rrs_dataset_release",
-            "rrs_submit", "rrs_wait", "rrs_ctx_get_stats", "rrs_depth_halfspace_noalloc"]
+            "rrs_submit", "rrs_wait", "rrs_ctx_get_stats", "rrs_depth_halfspace_noalloc",
+            "rrs_depth_mahalanobis"]
 
 
 class RRSError(RuntimeError):
@@ -115,6 +118,8 @@ def load(path: str = LIB_PATH):
     L.rrs_depth_projection.restype = ctypes.c_int
     L.rrs_depth_apd.argtypes = common + [ctypes.POINTER(rrs_opts)]
     L.rrs_depth_apd.restype = ctypes.c_int
+    L.rrs_depth_mahalanobis.argtypes = [p, i64, i64, p, i64, p, ctypes.POINTER(rrs_opts)]
+    L.rrs_depth_mahalanobis.restype = ctypes.c_int
     L.rrs_last_error.restype = ctypes.c_char_p
     L.rrs_release_workspace.restype = ctypes.c_int
     L.rrs_version.restype = ctypes.c_int32
@@ -175,7 +180,8 @@ def _alloc_like(X, shape, np_dtype, torch_dtype):
 
 
 def _run(fn_name, X, Z, K, n_refine, cap_shrink, seed, precision, query_offset,
-         want_count, want_poles, want_trace, stream, workspace_limit, graph=False):
+         want_count, want_poles, want_trace, stream, workspace_limit, graph=False,
+         first_cap=False, area_cap=False):
     import_torch = _is_torch(X) or _is_torch(Z)
     f64 = (np.float64, None)
     i64 = (np.int64, None)
@@ -217,7 +223,8 @@ def _run(fn_name, X, Z, K, n_refine, cap_shrink, seed, precision, query_offset,
     o.poles = ptr(poles)
     o.trace = ptr(trace)
     o.workspace_limit = int(workspace_limit or 0)
-    o.flags = RRS_FLAG_GRAPH if graph else 0
+    o.flags = ((RRS_FLAG_GRAPH if graph else 0) | (RRS_FLAG_FIRST_CAP if first_cap else 0)
+               | (RRS_FLAG_AREA_CAP if area_cap else 0))
     L = load()
     args = [Xp, n, d, Zp, nq, int(K), int(n_refine), float(cap_shrink), int(seed), ptr(depth)]
     if fn_name == "rrs_depth_halfspace":
@@ -236,26 +243,29 @@ def _run(fn_name, X, Z, K, n_refine, cap_shrink, seed, precision, query_offset,
 
 def rrs_depth_halfspace(X, Z, K, n_refine, cap_shrink, seed=0, precision="f64", query_offset=0,
                         want_poles=False, want_trace=False, stream=None, workspace_limit=0,
-                        graph=False):
+                        graph=False, first_cap=False, area_cap=False):
     """Halfspace depth of each row of Z; returns dict(depth, count[, poles, trace])."""
     return _run("rrs_depth_halfspace", X, Z, K, n_refine, cap_shrink, seed, precision,
-                query_offset, True, want_poles, want_trace, stream, workspace_limit, graph)
+                query_offset, True, want_poles, want_trace, stream, workspace_limit, graph,
+                first_cap, area_cap)
 
 
 def rrs_depth_projection(X, Z, K, n_refine, cap_shrink, seed=0, precision="f64", query_offset=0,
                          want_poles=False, want_trace=False, stream=None, workspace_limit=0,
-                         graph=False):
+                         graph=False, first_cap=False, area_cap=False):
     """Projection depth of each row of Z; returns dict(depth[, poles, trace])."""
     return _run("rrs_depth_projection", X, Z, K, n_refine, cap_shrink, seed, precision,
-                query_offset, False, want_poles, want_trace, stream, workspace_limit, graph)
+                query_offset, False, want_poles, want_trace, stream, workspace_limit, graph,
+                first_cap, area_cap)
 
 
 def rrs_depth_apd(X, Z, K, n_refine, cap_shrink, seed=0, precision="f64", query_offset=0,
                   want_poles=False, want_trace=False, stream=None, workspace_limit=0,
-                  graph=False):
+                  graph=False, first_cap=False, area_cap=False):
     """Asymmetric projection depth of each row of Z; returns dict(depth[, poles, trace])."""
     return _run("rrs_depth_apd", X, Z, K, n_refine, cap_shrink, seed, precision, query_offset,
-                False, want_poles, want_trace, stream, workspace_limit, graph)
+                False, want_poles, want_trace, stream, workspace_limit, graph, first_cap,
+                area_cap)
 
 
 def rrs_depth_halfspace_noalloc(X, Z, K, n_refine, cap_shrink, seed=0, precision="f64",
@@ -298,6 +308,36 @@ def rrs_depth_halfspace_noalloc(X, Z, K, n_refine, cap_shrink, seed=0, precision
         ctypes.c_void_p(out["depth"].data_ptr()),
         ctypes.c_void_p(cnt.data_ptr()) if cnt is not None else None, ctypes.byref(o)))
     return out
+
+
+def rrs_depth_mahalanobis(X, Z, stream=None):
+    """Mahalanobis depth D_M(L) of each row of Z (sample mean, maximum-likelihood
+    covariance of X); numpy arrays (host) or torch device tensors."""
+    f64 = (np.float64, None)
+    if _is_torch(X) or _is_torch(Z):
+        import torch
+        f64 = (np.float64, torch.float64)
+    Xp, Xk, Xdev = _prep(X, "X", f64)
+    Zp, Zk, Zdev = _prep(Z, "Z", f64)
+    if Xdev != Zdev:
+        raise ValueError("X and Z must both be host or both be device arrays")
+    n, d = int(Xk.shape[0]), int(Xk.shape[1])
+    nq = int(Zk.shape[0])
+    if int(Zk.shape[1]) != d:
+        raise ValueError("Z must have d columns")
+    o = rrs_opts()
+    if Xdev:
+        import torch
+        depth = torch.empty(nq, dtype=torch.float64, device=Xk.device)
+        o.device_ptrs = 1
+        s = stream if stream is not None else torch.cuda.current_stream(Xk.device)
+        o.stream = ctypes.c_void_p(s.cuda_stream if hasattr(s, "cuda_stream") else int(s))
+        dptr = ctypes.c_void_p(depth.data_ptr())
+    else:
+        depth = np.empty(nq, dtype=np.float64)
+        dptr = depth.ctypes.data_as(ctypes.c_void_p)
+    _check(load().rrs_depth_mahalanobis(Xp, n, d, Zp, nq, dptr, ctypes.byref(o)))
+    return depth
 
 
 DEPTH_FUNCS = {"halfspace": rrs_depth_halfspace, "projection": rrs_depth_projection,

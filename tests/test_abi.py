@@ -97,3 +97,14 @@ def test_serving_argument_errors_without_device():
     if not torch.cuda.is_available():
         st = L.rrs_ctx_create(None, ctypes.byref(out))
         assert st != rrs.RRS_OK and out.value is None
+
+
+def test_area_cap_flag_limits_rejected_without_device():
+    X = np.zeros((10, 3))
+    Z = np.zeros((2, 3))
+    with pytest.raises(rrs.RRSError) as ei:
+        rrs.rrs_depth_projection(X, Z, 10, 2, 1.0, area_cap=True)
+    assert ei.value.status == rrs.RRS_E_INVAL
+    with pytest.raises(rrs.RRSError) as ei:
+        rrs.rrs_depth_projection(X, Z, 10, 2, 0.5, area_cap=True, first_cap=True)
+    assert ei.value.status == rrs.RRS_E_INVAL

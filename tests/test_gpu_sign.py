@@ -127,3 +127,19 @@ def test_large_query_batch_items():
     with uneven lists."""
     w = workloads.small("halfspace", 5000, 8, 300, 200, 5, 0.6, law="mixture", seed_cfg=47)
     _check(w)
+
+
+@pytest.mark.parametrize("words", [4096, 6144])
+def test_queue_overflow_recounts_exactly(monkeypatch, words):
+    """A recheck queue too small for the uncertain rows (one entry or none
+    per wave segment, forced through the queue-size override) makes the
+    refinement recount in binary64: the results are unchanged."""
+    w = workloads.small("halfspace", 2000, 4, 16, 240, 6, 0.5, law="integer", seed_cfg=81)
+    X = w.X.copy()
+    X[500:900] = X[3]
+    w.X = X
+    Z = w.Z.copy()
+    Z[:8] = w.X[:8]
+    w.Z = Z
+    monkeypatch.setenv("RRS_QUEUE_WORDS", str(words))
+    _check(w)

@@ -242,3 +242,50 @@ def test_replay_cases_exercise_ties():
                         best, pole = vals[j], U[j]
                     phi *= 0.5
     assert tied >= 10 and equal >= 5
+
+
+@pytest.mark.parametrize("notion", ["halfspace", "projection", "apd"])
+def test_trajectory_replay_reproduces_the_oracle_chain(notion):
+    """oracle.rrs_replay (exact depths along a given trajectory) fed with the
+    oracle's own trajectory: every refinement's exact minimum is the traced
+    minimum, the chosen direction attains it, and the first exact argmin is
+    the traced index."""
+    rng = np.random.default_rng(7)
+    X = rng.standard_normal((150, 4))
+    z = rng.standard_normal(4) * 0.3
+    K, r = 60, 5
+    _, _, _, tr = oracle.rrs_query(notion, X, z, 2, K, r, 0.5, 3)
+    traj = np.array([[j, int(imp)] for j, imp, _ in tr], dtype=np.int64)
+    ex = oracle.rrs_replay(notion, X, z, 2, K, r, 0.5, 3, traj)
+    n = X.shape[0]
+    for l, (j, imp, v) in enumerate(tr):
+        want = v / n if notion == "halfspace" else v
+        assert ex[l, 0] == want and ex[l, 1] == want
+        assert int(ex[l, 2]) == j
+
+
+@pytest.mark.parametrize("notion", ["halfspace", "projection", "apd"])
+def test_first_cap_reading_replays_from_the_building_blocks(notion):
+    """RRS_FLAG_FIRST_CAP reading: refinement 1 draws from Alg. S4's cap of
+    half-angle pi/2 around e1 (a hemisphere), so every direction has u_1 >= 0
+    and the angle to e1 is (pi/2) U; with r = 1 the depth is the minimum of
+    the univariate depths over those directions."""
+    rng = np.random.default_rng(12)
+    X = rng.standard_normal((120, 5))
+    Z = rng.standard_normal((3, 5)) * 0.5
+    K = 40
+    got = oracle.rrs_depth_idx(notion, X, Z, np.arange(3), K, 1, 0.5, 7, first_cap=True)
+    e1 = np.zeros(5)
+    e1[0] = 1.0
+    for q in range(3):
+        best = None
+        for j in range(K):
+            u = oracle.direction(7, q, 1, j, 5, 1.0, e1, first_cap=True)
+            assert u[0] >= 0.0
+            assert abs(np.dot(u, u) - 1.0) < 1e-14
+            t = oracle.project(X, Z[q], u)
+            v = (oracle.uni_halfspace(t) / 120.0 if notion == "halfspace"
+                 else (oracle.uni_projection(t)[0] if notion == "projection"
+                       else oracle.uni_apd(t)[0]))
+            best = v if best is None or v < best else best
+        assert got["depth"][q] == min(best, 1.0)
