@@ -345,7 +345,8 @@ def main():
     t1 = time.perf_counter()
     prof = rrs.rrs_profile_read()
     counters = {c: rrs.rrs_profile_counter(c)
-                for c in ("select_fast", "select_fallback", "recheck_pairs", "gemm_pairs")}
+                for c in ("select_fast", "select_fallback", "recheck_pairs", "gemm_pairs",
+                          "shared_full", "shared_median", "shared_none")}
     rrs.rrs_profile_enable(False)
     depth = out["depth"].cpu().numpy()
 

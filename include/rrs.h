@@ -238,7 +238,12 @@ int32_t rrs_profile_read(rrs_kernel_stat *out, int32_t max_entries);
  * fallback (counted on the device); "select_fast": the other selects, taken as
  * two per projection / APD column (an APD column without positive deviations
  * has one); "recheck_pairs": (query,
- * direction, point) projections the matrix-core forms recomputed in binary64.
+ * direction, point) projections the matrix-core forms recomputed in binary64;
+ * "gemm_pairs": projections the halfspace sign GEMM evaluated (the others
+ * were decided by the cap bound); "shared_full", "shared_median",
+ * "shared_none": streamed APD columns whose shared passes served the whole
+ * column, only its median, or nothing (the rest then took the separate
+ * selects).
  * Returns 0 and writes *value, or -1 for an unknown name or NULL pointer. */
 int32_t rrs_profile_counter(const char *name, double *value);
 

@@ -343,9 +343,10 @@ rrs_status run(int notion, const double *X, int64_t n, int64_t d, const double *
         g_prof.collect();
         for (uint32_t *sp : pstats) {
             if (!sp) continue;
-            uint32_t hs[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+            uint32_t hs[rrs::kStatWords] = {};
             RRS_HIP_TRY(hipMemcpy(hs, sp, sizeof(hs), hipMemcpyDeviceToHost));
             g_prof.sel_fallback += hs[1];
+            for (int w = 0; w < 3; ++w) g_prof.shared[w] += hs[8 + w];
             uint64_t rp = 0, gp = 0;
             std::memcpy(&rp, hs + 4, sizeof(rp));
             std::memcpy(&gp, hs + 6, sizeof(gp));
@@ -491,6 +492,12 @@ int32_t rrs_profile_counter(const char *name, double *value)
         *value = g_prof.gemm_pairs;
         return 0;
     }
+    static const char *const kShared[3] = {"shared_full", "shared_median", "shared_none"};
+    for (int w = 0; w < 3; ++w)
+        if (std::strcmp(name, kShared[w]) == 0) {
+            *value = g_prof.shared[w];
+            return 0;
+        }
     return -1;
 }
 

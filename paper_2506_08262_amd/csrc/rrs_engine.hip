@@ -85,6 +85,7 @@ void Profiler::clear()
         work[k] = 0.0;
     }
     sel_total = sel_fallback = recheck_pairs = gemm_pairs = 0.0;
+    shared[0] = shared[1] = shared[2] = 0.0;
 }
 
 namespace {
@@ -242,6 +243,7 @@ int job_sizes(const JobSpec &s, int64_t n, int64_t d, const Plan &p, int64_t qb,
     sz[k++] = p.cull ? (size_t)qb * 4 : 0;                      // lcount
     sz[k++] = p.cull ? (size_t)qb * 8 : 0;                      // base
     sz[k++] = p.cull ? (size_t)(qb + 1) * 4 : 0;                // offs
+    sz[k++] = p.cull ? (size_t)sign_max_items(qb, n, p.m, p.rpi) * 16 : 0;  // items
     return k;
 }
 
@@ -282,10 +284,10 @@ rrs_status job_plan(const JobSpec &s, int64_t n, int64_t d, size_t limit, Plan *
         if ((double)n * rowb < 2147483648.0 && cols * rowb < 2147483648.0 &&
             (double)hi * (double)p.m < 2147483648.0) {
             p.sign = true;
-            // culling's list-mode items must stay below 2^31
+            // culling's item table (16 bytes per item) must stay below 2 GiB
             const double items = (double)hi * ((double)n / 256.0 + 1.0) *
                                  (double)((p.m + 127) / 128);
-            p.cull = env_flag("RRS_CULL", true) && items < 2147483648.0;
+            p.cull = env_flag("RRS_CULL", true) && items < 134217728.0;
         }
     }
     // largest batch whose workspace fits the limit (the size grows with qb)
@@ -354,8 +356,12 @@ rrs_status enqueue_job(const JobSpec &s, const DataDev &D, const Plan &p, const 
     uint32_t *lcount = cv.take<uint32_t>(sz[22] / 4);
     uint32_t *base = cv.take<uint32_t>(sz[23] / 4);
     uint32_t *offs = cv.take<uint32_t>(sz[24] / 4);
+    uint32_t *items = cv.take<uint32_t>(sz[25] / 4);
     const int64_t npad_pole = p.cull ? mfma_col_pad(qb) : 0;
     const double cull_angle = env_double("RRS_CULL_ANGLE", 1.5707963267948966);
+    // lists when their matrix-core work is below this percent of the dense
+    // GEMM's (RRS_LIST_PCT: 0 always dense, 1000 always lists)
+    const int list_pct = (int)env_double("RRS_LIST_PCT", 80.0);
     if (stats_out) *stats_out = stats;
     if (profiling) RRS_HIP_TRY(launch_fill_u32(stats, kStatWords, 0u, st));
 
@@ -383,7 +389,7 @@ rrs_status enqueue_job(const JobSpec &s, const DataDev &D, const Plan &p, const 
                                              B0, B1, cmarg, D.amax, nullptr, nullptr, st));
                 SignArgs sa{n,     d,     D.A0,  D.A1,   D.anorm, B0,     B1,     cmarg,
                             npad,  m,     ldm,   nb,     cnt,     queue,  qctl,   p.qcap,
-                            UT,    Zb,    nullptr, nullptr, nullptr, p.rpi};
+                            UT,    Zb,    nullptr, nullptr, nullptr, nullptr, nullptr, p.rpi};
                 const bool cull_l = p.cull && l >= 2 && 1.5707963267948966 * phi <= cull_angle;
                 if (cull_l) {
                     RRS_HIP_TRY(launch_mfma_dirs(p.prec, true, pole, d, 1, 1, nb, npad_pole, Zb,
@@ -393,7 +399,7 @@ rrs_status enqueue_job(const JobSpec &s, const DataDev &D, const Plan &p, const 
                     RRS_HIP_TRY(launch_fill_u32(base, nb * 2, 0u, st));
                     CullArgs ca{pole,  D.xbar, P0,     P1,   pmarg,
                                 npad_pole, lam, mu,   lists, lcount,
-                                base,  offs,
+                                base,  offs,  items, qctl + 4, list_pct,
                                 profiling ? (unsigned long long *)(stats + 6) : nullptr};
                     {
                         ProfScope ps(prof, K_CULL, (double)nb * (double)n, st);
@@ -402,6 +408,8 @@ rrs_status enqueue_job(const JobSpec &s, const DataDev &D, const Plan &p, const 
                     sa.lists = lists;
                     sa.lcount = lcount;
                     sa.offs = offs;
+                    sa.items = items;
+                    sa.mode = qctl + 4;
                 } else {
                     RRS_HIP_TRY(launch_fill_u32(cnt, nb * ldm * 2, 0u, st));
                     if (profiling) prof->gemm_pairs += proj_units;

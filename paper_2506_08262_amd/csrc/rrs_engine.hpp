@@ -70,6 +70,9 @@ struct Profiler {
     // without culling (counted on the host), the listed points' pairs after
     // culling (counted on the device, stats words 6..7)
     double gemm_pairs = 0.0;
+    // streamed APD columns whose shared passes served the whole column,
+    // only the median, or nothing (stats words 8..10)
+    double shared[3] = {0.0, 0.0, 0.0};
     hipEvent_t get();
     // makes room for two more events (waits for the recorded launches)
     void reserve2();

@@ -144,8 +144,11 @@ struct SignArgs {
     uint64_t qcap;
     const double *UT;          // [qb][d][ldm] binary64 directions (cull bounds, recheck)
     const double *Z;           // [qb][d]
-    // list mode: the undecided points of each query (null: every point)
-    const uint32_t *lists, *lcount, *offs;
+    // list mode: the undecided points of each query (null: every point), and
+    // the items of the list-mode GEMM (four words each: q | tile << 16, first
+    // and end list position)
+    const uint32_t *lists, *lcount, *offs, *items;
+    const uint32_t *mode;      // list mode only when *mode != 0 (written by launch_cull)
     int rpi;                   // point tiles of 256 per list-mode item
 };
 struct CullArgs {
@@ -159,9 +162,17 @@ struct CullArgs {
     uint32_t *lcount;          // [qb] out (zeroed by the caller)
     uint32_t *base;            // [qb][2] out: decided points below / above (zeroed)
     uint32_t *offs;            // [qb + 1] out: item offsets of the list-mode GEMM
+    uint32_t *items;           // [sign_max_items][4] out: the items themselves
+    uint32_t *mode;            // out: 1 = the sign GEMM runs over the lists, 0 = dense
+    int list_pct;              // lists when their work is below this percent of dense
     unsigned long long *pairs; // optional: adds sum_q lcount_q * m (pairs the GEMM evaluates)
 };
 bool sign_supported(int prec, int64_t d);
+// Most items the list-mode sign GEMM can have (every point undecided).
+inline int64_t sign_max_items(int64_t qb, int64_t n, int64_t m, int rpi)
+{
+    return qb * ((n + 256 * (int64_t)rpi - 1) / (256 * (int64_t)rpi)) * ((m + 127) / 128);
+}
 // A queue segment of the sign GEMM that overflowed sets this bit of *qcount
 // (the queue's words are split into one segment per wave of its grid).
 constexpr uint32_t kSignQueueOverflow = 0x80000000u;

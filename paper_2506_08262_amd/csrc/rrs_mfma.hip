@@ -121,17 +121,22 @@ __global__ __launch_bounds__(64) void k_prep_dirs(const double *__restrict__ UT,
 {
     const int64_t J = (int64_t)blockIdx.x * 64 + threadIdx.x;
     if (J >= npad) return;
-    const int64_t off = J * kp;
-    __bf16 *bh = (__bf16 *)B0 + off;
-    __bf16 *bl = (__bf16 *)B1 + off;
-    float *bf = (float *)B0 + off;
+    // a thread writes its operand row in 16-byte pieces (8 bf16 or 4 binary32
+    // elements; kp is a multiple of 16 or 8, rows start 16-byte aligned)
+    constexpr int kE = PREC == MFMA_BF16 ? 8 : 4;
+    typedef __attribute__((ext_vector_type(8))) __bf16 v8bf;
+    typedef __attribute__((ext_vector_type(4))) float v4f;
+    const int64_t pieces = kp / kE;
+    v8bf *h8 = (v8bf *)B0 + J * pieces;
+    v8bf *l8 = (v8bf *)B1 + J * pieces;
+    v4f *f4 = (v4f *)B0 + J * pieces;
     if (J >= ncols) {
-        for (int64_t c = 0; c < kp; ++c) {
+        for (int64_t g = 0; g < pieces; ++g) {
             if (PREC == MFMA_BF16) {
-                bh[c] = (__bf16)0.0f;
-                bl[c] = (__bf16)0.0f;
+                h8[g] = v8bf{};
+                l8[g] = v8bf{};
             } else {
-                bf[c] = 0.0f;
+                f4[g] = v4f{};
             }
         }
         if (FOLD) {
@@ -146,37 +151,39 @@ __global__ __launch_bounds__(64) void k_prep_dirs(const double *__restrict__ UT,
     const double *u = UT + qi * d * ldm + j;
     const double *z = Zb + qi * d;
     double cj = 0.0, bn = 0.0;
-    for (int64_t c = 0; c < d; ++c) {
-        const double uc = u[c * ldm];
-        const double b = z[c] - xbar[c];
-        cj = fma(b, uc, cj);
-        bn = fma(b, b, bn);
-        if (PREC == MFMA_BF16) {
-            const __bf16 h = to_bf16(uc);
-            bh[c] = h;
-            bl[c] = to_bf16(uc - from_bf16(h));
-        } else {
-            bf[c] = (float)uc;
+    for (int64_t g = 0; g < pieces; ++g) {
+        v8bf vh{}, vl{};
+        v4f vf{};
+#pragma unroll
+        for (int e = 0; e < kE; ++e) {
+            const int64_t c = g * kE + e;
+            if (c < d) {
+                const double uc = u[c * ldm];
+                const double b = z[c] - xbar[c];
+                cj = fma(b, uc, cj);
+                bn = fma(b, b, bn);
+                if (PREC == MFMA_BF16) {
+                    const __bf16 h = to_bf16(uc);
+                    vh[e] = h;
+                    vl[e] = to_bf16(uc - from_bf16(h));
+                } else {
+                    vf[e] = (float)uc;
+                }
+            } else if (FOLD && c == d) {
+                // the centring term -c_j (bf16: hi in column d, lo in d + 1)
+                if (PREC == MFMA_BF16)
+                    vh[e] = to_bf16(-cj);
+                else
+                    vf[e] = (float)(-cj);
+            } else if (FOLD && PREC == MFMA_BF16 && c == d + 1) {
+                vh[e] = to_bf16(-cj - from_bf16(to_bf16(-cj)));
+            }
         }
-    }
-    int64_t c0 = d;
-    if (FOLD && PREC == MFMA_BF16) {
-        const __bf16 ch = to_bf16(-cj);
-        bh[d] = ch;
-        bh[d + 1] = to_bf16(-cj - from_bf16(ch));
-        bl[d] = (__bf16)0.0f;
-        bl[d + 1] = (__bf16)0.0f;
-        c0 = d + 2;
-    } else if (FOLD) {
-        bf[d] = (float)(-cj);
-        c0 = d + 1;
-    }
-    for (int64_t c = c0; c < kp; ++c) {
         if (PREC == MFMA_BF16) {
-            bh[c] = (__bf16)0.0f;
-            bl[c] = (__bf16)0.0f;
+            h8[g] = vh;
+            l8[g] = vl;
         } else {
-            bf[c] = 0.0f;
+            f4[g] = vf;
         }
     }
     // margin part that depends on the direction only: kappa |c_j| plus the

@@ -802,16 +802,18 @@ __device__ __forceinline__ bool rc_select(const Col &C, const SRC &src, double m
 
 
 // ---------------------------------------------------------------------------
-// Shared passes for streamed columns (n > 16384, reread from HBM by every
-// pass).  Asymmetric projection depth: one pass bins the brackets of both the
-// median and the MAD_+ rank, one pass collects both windows' candidates; the
-// MAD_+ rank is that of the tie-free count #{t <= med} (ceil(n / 2)), which
-// the median's window then confirms.  Projection depth: the MAD's histogram is
-// built in the median's window pass, binning |s - m~| around the centre m~ of
-// the median's window instead of the exact median; the rank statistic moves
-// by at most |m~ - med|, which widens the MAD's window.  Whatever these cannot
-// serve (a bracket that misses, target bins that hold too many values for one
-// window, ties at the median) is left to the separate selects.
+// ---------------------------------------------------------------------------
+// Shared passes for streamed APD columns (n > 16384, reread from HBM by every
+// pass): one pass bins the brackets of both the median and the MAD_+ rank,
+// one pass collects both windows' candidates; the MAD_+ rank is that of the
+// tie-free count #{t <= med} (ceil(n / 2)), which the median's window then
+// confirms.  Whatever this cannot serve (a bracket that misses, target bins
+// that hold too many values for one window, ties at the median) is left to
+// the separate selects.  (Projection depth keeps the separate selects: its
+// MAD's histogram would have to be binned around an approximation of the
+// median, and the resulting window, wider by half a median bin, held so many
+// candidates that their binary64 recomputation cost more than the saved
+// pass.)
 // ---------------------------------------------------------------------------
 struct Target {
     float scale, off;    // linear bins of the bracket
@@ -1063,106 +1065,6 @@ __device__ __forceinline__ int rc_apd_shared(const Col &C, const StreamSrc<G> &s
     return 2;
 }
 
-// Projection depth of a streamed column: median histogram, then the median's
-// window pass also bins the MAD's approximations, then the MAD's window.
-// Returns 2 with D when this served the whole column, 1 with the exact
-// median when only the median's part served, 0 when nothing was decided.
-template <bool EXACT, class G, class SH>
-__device__ __forceinline__ int rc_proj_shared(const Col &C, const StreamSrc<G> &src, SH &sh, double &D,
-                              double &med_out)
-{
-    const int tid = G::tid();
-    constexpr uint32_t kCap = (uint32_t)SH::kCap;
-    const int64_t n = C.n;
-    if (!C.sane) return 0;
-    const bool odd = (n & 1) != 0;
-    const uint64_t k = odd ? (uint64_t)n / 2 : (uint64_t)n / 2 - 1;
-    for (int x = tid; x < kHistN; x += G::kN) {
-        sh.hist[x] = 0;
-        sh.hist2[x] = 0;
-    }
-    if (tid == 0) {
-        sh.ncand = sh.nlow = sh.ncand2 = sh.nlow2 = 0;
-    }
-    take_samples<0, G>(src, 0.0f, sh);
-    Target t1, t2;
-    if (!sample_bracket(sh, n, k, !odd, t1.scale, t1.off)) return 0;
-    const int lane = tid & 63;
-    const float lo_l = -(float)(lane + 1), hi_l = (float)(kBins + lane);
-    {
-        uint32_t *const b1 = sh.hist + kHistLo;
-        src.each([&](int, float sv) {
-            atomicAdd(&b1[lin_slot(sv, t1.scale, t1.off, lo_l, hi_l)], 1u);
-        });
-    }
-    G::sync();
-    if (!hist_target<SH>(sh.hist, k, !odd, t1)) return 0;
-    target_window(t1, C.E);
-    // the median (shifted by c) lies in [vlo - E, vhi + E]; its centre m~ is
-    // within dm of it
-    const double vlo = lin_lo(t1.bA, t1.scale, t1.off), vhi = lin_hi(t1.bB, t1.scale, t1.off);
-    const double mt = 0.5 * (vlo + vhi);
-    const float mtf = (float)mt;
-    const double dm = 0.5 * (vhi - vlo) + C.E + fabs(mt - (double)mtf);
-    // the MAD's bracket from the samples' deviations from m~ (binary32)
-    take_samples<1, G>(src, mtf, sh);
-    const bool ok2 = sample_bracket(sh, n, k, !odd, t2.scale, t2.off);
-    // pass 2: the median's candidates and the MAD's histogram of |s - m~|
-    {
-        const float fA1 = (float)t1.bA;
-        uint32_t *const b2 = sh.hist2 + kHistLo;
-        src.each([&](int i, float x) {
-            if (fabsf(x - t1.midf) <= t1.hwf) {
-                if (fmaf(x, t1.scale, t1.off) < fA1) atomicAdd(&sh.nlow, 1u);
-                const uint32_t p = atomicAdd(&sh.ncand, 1u);
-                if (p < kCap) sh.cidx[p] = (uint32_t)i;
-            }
-            if (ok2) atomicAdd(&b2[lin_slot(fabsf(x - mtf), t2.scale, t2.off, lo_l, hi_l)], 1u);
-        });
-    }
-    G::sync();
-    const uint32_t nc1 = sh.ncand;
-    const uint64_t B1 = (uint64_t)t1.beforeA - sh.nlow;
-    G::sync();
-    if (!(nc1 <= kCap && B1 <= k && k + (odd ? 0 : 1) < B1 + nc1)) return 0;
-    double a, b;
-    rank_candidates<0, EXACT, G>(C, sh.cidx, nc1, 0.0, k - B1, !odd, sh, a, b);
-    const double med = odd ? a : (a + b) * 0.5;
-    med_out = med;
-    if (!ok2 || !hist_target<SH>(sh.hist2, k, !odd, t2)) return 1;
-    // |s - m~| in binary32 is within E + dm of |t - med|, plus the roundings
-    // of the difference
-    const double vlo2 = lin_lo(t2.bA, t2.scale, t2.off), vhi2 = lin_hi(t2.bB, t2.scale, t2.off);
-    const double Ew = (C.E + dm) * 1.000001 +
-                      0x1p-22 * (fabs(mt) + fabs(vlo2) + fabs(vhi2) + C.E + dm) + 1e-300;
-    target_window(t2, Ew);
-    // pass 3: the MAD's candidates
-    {
-        const float fA2 = (float)t2.bA;
-        src.each([&](int i, float sv) {
-            const float x = fabsf(sv - mtf);
-            if (fabsf(x - t2.midf) <= t2.hwf) {
-                if (fmaf(x, t2.scale, t2.off) < fA2) atomicAdd(&sh.nlow2, 1u);
-                const uint32_t p = atomicAdd(&sh.ncand2, 1u);
-                if (p < kCap) sh.cidx2[p] = (uint32_t)i;
-            }
-        });
-    }
-    G::sync();
-    const uint32_t nc2 = sh.ncand2;
-    const uint64_t B2 = (uint64_t)t2.beforeA - sh.nlow2;
-    G::sync();
-    if (!(nc2 <= kCap && B2 <= k && k + (odd ? 0 : 1) < B2 + nc2)) return 1;
-    double m1, m2;
-    rank_candidates<1, EXACT, G>(C, sh.cidx2, nc2, med, k - B2, !odd, sh, m1, m2);
-    const double mad = odd ? m1 : (m1 + m2) * 0.5;
-    if (mad == 0.0)
-        D = (med == 0.0) ? 1.0 : 0.0;
-    else
-        D = 1.0 / (1.0 + fabs(med) / mad);
-    return 2;
-}
-
 // Number of points with t <= med: from the median's window when it served,
 // else by a counting pass over recomputed values.
 template <bool EXACT, class G, class SH>
@@ -1200,12 +1102,11 @@ __device__ __forceinline__ double rc_depth(const Col &C, const SRC &src, SH &sh,
     double med = 0.0;
     bool have_med = false;
     uint64_t nle_sh = 0;
-    if constexpr (SRC::kMaxLevel > 0 && SH::kShared) {
-        // streamed column: the order statistics share passes
+    if constexpr (SRC::kMaxLevel > 0 && SH::kShared && NOTION == NOTION_APD) {
+        // streamed APD column: the order statistics share passes
         double D;
-        const int st = NOTION == NOTION_APD
-                           ? rc_apd_shared<EXACT, G>(C, src, sh, D, med, nle_sh)
-                           : rc_proj_shared<EXACT, G>(C, src, sh, D, med);
+        const int st = rc_apd_shared<EXACT, G>(C, src, sh, D, med, nle_sh);
+        if (stats && G::tid() == 0) atomicAdd(&stats[8 + (2 - st)], 1u);
         if (st == 2) return D;
         have_med = st == 1;
         G::sync();
@@ -1309,8 +1210,9 @@ __global__ __launch_bounds__(G::kN) void k_select_rc(const float *__restrict__ S
                                                      double *__restrict__ Dj,
                                                      uint32_t *__restrict__ stats)
 {
-    // streamed columns (VPT == 0) carry the second histogram and list
-    using SH = typename std::conditional<VPT == 0, RcSharedS<CAP, STG>, RcShared<CAP, STG>>::type;
+    // streamed APD columns (VPT == 0) carry the second histogram and list
+    using SH = typename std::conditional<VPT == 0 && NOTION == NOTION_APD, RcSharedS<CAP, STG>,
+                                         RcShared<CAP, STG>>::type;
     __shared__ SH sh;
     select_column<NOTION, EXACT, VPT, G, SH>(S, n, m, ldm, cq, eq, X, d, Zb, UT, Dj, stats, sh);
 }

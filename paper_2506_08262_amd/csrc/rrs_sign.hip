@@ -65,7 +65,9 @@ struct SignParams {
     int32_t npad, ncols;       // operand rows; live flat columns
     int32_t m, ldm, qb;        // directions per query, count stride, queries
     float kappa_a;             // data part of the margin (times |a_i|)
-    int32_t rpi;               // point tiles per item
+    int32_t rpi;               // point tiles per item (list mode)
+    int32_t rpi_dense;         // point tiles per item (dense mode)
+    const uint32_t *mode;      // list mode only when *mode != 0 (null: lists decide)
     // sign epilogue: counts, and per wave of the grid a queue segment of
     // `seg` entries (two words each) with its fill in segcnt; a segment that
     // overflows sets bit 31 of *qflag
@@ -78,6 +80,7 @@ struct SignParams {
     const uint32_t *lists;     // [qb][n] undecided points per query
     const uint32_t *lcount;    // [qb]
     const uint32_t *offs;      // [qb + 1] first item of each query; offs[qb] = total
+    const uint32_t *items;     // [total][4] q | tile << 16, first and end list position
     // cull epilogue (columns are the queries' poles)
     const float *lam, *mu;     // [qb] threshold = |a_i| lam_q + mu_q
     uint32_t *lists_out;       // [qb][n]
@@ -100,6 +103,11 @@ __device__ __forceinline__ bf16x8 ld_b128(Rsrc r, uint32_t off)
 __device__ __forceinline__ uint32_t ld_u32(Rsrc r, uint32_t off)
 {
     return __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0);
+}
+typedef __attribute__((ext_vector_type(4))) uint32_t u32x4;
+__device__ __forceinline__ u32x4 ld_u32x4(Rsrc r, uint32_t off)
+{
+    return __builtin_bit_cast(u32x4, __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0));
 }
 __device__ __forceinline__ float ld_f32(Rsrc r, uint32_t off)
 {
@@ -188,24 +196,41 @@ __device__ __forceinline__ void wave_mma(Rsrc A0, Rsrc A1, const uint32_t (&idx)
             al[stg][rt] = ld_b128(A1, aoff[rt] + ks * 32);
         }
     };
+    // B fragments one (K step, column tile) ahead: the LDS reads of step
+    // s + 1 are in flight during the MFMAs of step s
+    bf16x8 bh[2], bl[2];
+    auto ldb = [&](int ks, int ct, int buf) {
+        const int col = ct * 32 + lr;
+        bh[buf] = L.b[0][col][2 * ks + lh];
+        bl[buf] = L.b[1][col][2 * ks + lh];
+    };
     load(0, 0);
+    ldb(0, 0, 0);
 #pragma unroll
     for (int ks = 0; ks < KS; ++ks) {
         const int stg = ks & 1;
         if (ks + 1 < KS) load(ks + 1, stg ^ 1);
 #pragma unroll
         for (int ct = 0; ct < 4; ++ct) {
-            const int col = ct * 32 + lr;
-            const bf16x8 bh = L.b[0][col][2 * ks + lh];
-            const bf16x8 bl = L.b[1][col][2 * ks + lh];
+            const int cur = (ks * 4 + ct) & 1;
+            const bool more = ct < 3 || ks + 1 < KS;
+            if (ct < 3)
+                ldb(ks, ct + 1, cur ^ 1);
+            else if (ks + 1 < KS)
+                ldb(ks + 1, 0, cur ^ 1);
+            // issue order: the next step's B reads (and, at ct = 0, the next
+            // K step's A loads), then this step's six MFMAs
+            if (ct == 0 && ks + 1 < KS) __builtin_amdgcn_sched_group_barrier(0x020, 4, 0);
+            if (more) __builtin_amdgcn_sched_group_barrier(0x100, 2, 0);
+            __builtin_amdgcn_sched_group_barrier(0x008, 6, 0);
 #pragma unroll
             for (int rt = 0; rt < 2; ++rt) {
-                acc[rt][ct] =
-                    __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[stg][rt], bh, acc[rt][ct], 0, 0, 0);
-                acc[rt][ct] =
-                    __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[stg][rt], bl, acc[rt][ct], 0, 0, 0);
-                acc[rt][ct] =
-                    __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[stg][rt], bh, acc[rt][ct], 0, 0, 0);
+                acc[rt][ct] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[stg][rt], bh[cur],
+                                                                      acc[rt][ct], 0, 0, 0);
+                acc[rt][ct] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[stg][rt], bl[cur],
+                                                                      acc[rt][ct], 0, 0, 0);
+                acc[rt][ct] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[stg][rt], bh[cur],
+                                                                      acc[rt][ct], 0, 0, 0);
             }
             // keep the scheduler from hoisting every column tile's operands
             __builtin_amdgcn_sched_barrier(0);
@@ -233,28 +258,50 @@ __device__ __forceinline__ float wave_max(float v)
     return v;
 }
 
-// Signs of one wave tile against the margin M[ct] of this lane's columns, as
-// bit masks over the lane half's 32 rows (bit 16 rt + r): rows with t^ above
-// the margin (above) and rows with |t^| above it (sure).  The tests take sign
-// bits of differences (M - v < 0 exactly when v > M: a difference of two
-// binary32 values is zero only when they are equal), so they stay in vector
-// registers; a NaN, were there one, would not read as sure.
-__device__ __forceinline__ void tile_signs(const f32x16 (&acc)[2][4], const float (&M)[4],
-                                           uint32_t (&above)[4], uint32_t (&sure)[4])
+// Signs of column tile ct of a wave tile against the margin M of this lane's
+// column, as bit masks over the lane half's 32 rows (bit 16 rt + r): rows
+// with t^ above the margin (above) and rows with |t^| above it (sure).  The
+// tests take sign bits of differences (M - v < 0 exactly when v > M: a
+// difference of two binary32 values is zero only when they are equal), so
+// they stay in vector registers; a NaN, were there one, would not read as
+// sure.
+__device__ __forceinline__ void column_masks(const f32x16 (&acc)[2][4], int ct, float M,
+                                             uint32_t &above, uint32_t &sure)
 {
+    above = 0u;
+    sure = 0u;
 #pragma unroll
     for (int rt = 0; rt < 2; ++rt)
 #pragma unroll
         for (int r = 0; r < 16; ++r) {
             const int k = rt * 16 + r;
-#pragma unroll
-            for (int ct = 0; ct < 4; ++ct) {
-                const float v = acc[rt][ct][r];
-                above[ct] |= (__float_as_uint(M[ct] - v) >> 31) << k;
-                sure[ct] |= (__float_as_uint(M[ct] - fabsf(v)) >> 31) << k;
-            }
-            __builtin_amdgcn_sched_barrier(0);  // a row at a time: bounded live ranges
+            const float v = acc[rt][ct][r];
+            above |= (__float_as_uint(M - v) >> 31) << k;
+            sure |= (__float_as_uint(M - fabsf(v)) >> 31) << k;
+            if ((r & 3) == 3) __builtin_amdgcn_sched_barrier(0);  // bounded live ranges
         }
+}
+
+// Cheap statistics of column tile ct against the margin M: whether all of
+// the lane half's 32 rows have |t^| above M (bit 31 of the AND of the bit
+// patterns of M - |t^|), and how many have the sign bit of t^ set.
+__device__ __forceinline__ void column_stats(const f32x16 (&acc)[2][4], int ct, float M,
+                                             bool &certain, uint32_t &nneg)
+{
+    uint32_t all = 0xFFFFFFFFu, c0 = 0u, c1 = 0u;
+#pragma unroll
+    for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+        for (int r = 0; r < 16; r += 4) {
+            const float v0 = acc[rt][ct][r], v1 = acc[rt][ct][r + 1];
+            const float v2 = acc[rt][ct][r + 2], v3 = acc[rt][ct][r + 3];
+            all &= __float_as_uint(M - fabsf(v0)) & __float_as_uint(M - fabsf(v1));
+            all &= __float_as_uint(M - fabsf(v2)) & __float_as_uint(M - fabsf(v3));
+            c0 += (__float_as_uint(v0) >> 31) + (__float_as_uint(v1) >> 31);
+            c1 += (__float_as_uint(v2) >> 31) + (__float_as_uint(v3) >> 31);
+        }
+    certain = (all >> 31) != 0u;
+    nneg = c0 + c1;
 }
 
 // Rows of the wave tile that lane half lh holds (bit 16 rt + r) below wl.
@@ -280,36 +327,37 @@ __global__ __launch_bounds__(256, 2) void k_sign(SignParams P)
     __shared__ SignLds<KS> L;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int lr = lane & 31, lh = lane >> 5;
-    const bool list = P.lists != nullptr;
+    const bool list = P.lists != nullptr && (P.mode == nullptr || *P.mode != 0u);
     const uint32_t rowb = (uint32_t)(KS * 32);  // bytes per operand row
     const Rsrc A0 = rsrc(P.A0, (uint32_t)P.n * rowb), A1 = rsrc(P.A1, (uint32_t)P.n * rowb);
     const Rsrc B0 = rsrc(P.B0, (uint32_t)P.npad * rowb), B1 = rsrc(P.B1, (uint32_t)P.npad * rowb);
     const Rsrc AN = rsrc(P.anorm, (uint32_t)P.n * 4u), CM = rsrc(P.cmarg, (uint32_t)P.npad * 4u);
-    const int32_t rows_per_item = kTM * P.rpi;
+    const int32_t rows_per_item = kTM * (list ? P.rpi : P.rpi_dense);
     // items: list mode (query, point chunk, direction tile of the query);
     // otherwise (point chunk, direction tile over the flat columns)
     const int32_t nct_all = (P.ncols + kTN - 1) / kTN;
-    const int32_t nctq = (P.m + kTN - 1) / kTN;
     const int32_t total = list ? (int32_t)P.offs[P.qb]
                                : ((P.n + rows_per_item - 1) / rows_per_item) * nct_all;
     const Sched sc = schedule(total);
     const uint32_t gw = blockIdx.x * 4u + (uint32_t)wave;  // this wave's queue segment
     uint64_t *const myq = P.queue + 2ull * (uint64_t)gw * (uint64_t)P.seg;
     uint32_t nq = 0;
+    // list mode: the item records, each loaded one item ahead
+    const Rsrc IT = rsrc(P.items, list ? (uint32_t)total * 16u : 0u);
+    u32x4 rec = ld_u32x4(IT, (uint32_t)sc.lo * 16u);
     for (int32_t it = sc.lo; it < sc.hi; it += sc.step) {
         int32_t J0, jend, rbeg, rend;
         Rsrc LS = rsrc(nullptr, 0u);
+        const u32x4 cur = rec;
+        if (list && it + sc.step < sc.hi) rec = ld_u32x4(IT, (uint32_t)(it + sc.step) * 16u);
         if (list) {
-            const int32_t q = item_query(P.offs, P.qb, it);
-            const int32_t loc = it - (int32_t)P.offs[q];
-            const int32_t rc = loc / nctq, ct = loc - rc * nctq;
+            const int32_t q = (int32_t)(cur[0] & 0xFFFFu), ct = (int32_t)(cur[0] >> 16);
             J0 = q * P.m + ct * kTN;
             const int32_t je = (ct + 1) * kTN < P.m ? (ct + 1) * kTN : P.m;
             jend = q * P.m + je;
-            rbeg = rc * rows_per_item;
-            const int32_t lc = (int32_t)P.lcount[q];
-            rend = rbeg + rows_per_item < lc ? rbeg + rows_per_item : lc;
-            LS = rsrc(P.lists + (size_t)q * (size_t)P.n, (uint32_t)lc * 4u);
+            rbeg = (int32_t)cur[1];
+            rend = (int32_t)cur[2];
+            LS = rsrc(P.lists + (size_t)q * (size_t)P.n, (uint32_t)rend * 4u);
         } else {
             const int32_t rc = it / nct_all, ct = it - rc * nct_all;
             J0 = ct * kTN;
@@ -329,38 +377,67 @@ __global__ __launch_bounds__(256, 2) void k_sign(SignParams P)
         }
         __syncthreads();
         uint32_t pos[4] = {0u, 0u, 0u, 0u}, neg[4] = {0u, 0u, 0u, 0u};
+        // point indices of this wave's rows of a tile (list mode: read from
+        // the query's list), fetched one tile ahead so that the A loads do
+        // not wait on the list; the norms follow once the indices are in
+        auto rows_of = [&](int32_t t0, uint32_t (&ix)[2]) {
+            const int32_t r0 = t0 + wave * 64;
+#pragma unroll
+            for (int rt = 0; rt < 2; ++rt) {
+                const int32_t pr = r0 + rt * 32 + lr;
+                const uint32_t prc = (uint32_t)(pr < rend ? pr : rbeg);
+                ix[rt] = list ? ld_u32(LS, prc * 4u) : prc;
+            }
+        };
+        uint32_t idx[2];
+        rows_of(rbeg, idx);
         for (int32_t t0 = rbeg; t0 < rend; t0 += kTM) {
             const int32_t r0 = t0 + wave * 64;
             const int wl = rend - r0 >= 64 ? 64 : (rend - r0 > 0 ? rend - r0 : 0);
-            if (wl == 0) continue;  // wave-uniform: this wave has no rows in the tile
-            uint32_t idx[2];
+            uint32_t nidx[2] = {0u, 0u};
+            if (t0 + kTM < rend) rows_of(t0 + kTM, nidx);
+            if (wl == 0) {  // wave-uniform: this wave has no rows in the tile
+                idx[0] = nidx[0];
+                idx[1] = nidx[1];
+                continue;
+            }
             float an = 0.0f;
 #pragma unroll
             for (int rt = 0; rt < 2; ++rt) {
-                const int wr = rt * 32 + lr;
-                const uint32_t pr = (uint32_t)(r0 + (wr < wl ? wr : 0));
-                idx[rt] = list ? ld_u32(LS, pr * 4u) : pr;
                 const float a = ld_f32(AN, idx[rt] * 4u);
-                if (wr < wl) an = fmaxf(an, a);
+                if (rt * 32 + lr < wl) an = fmaxf(an, a);
             }
             f32x16 acc[2][4];
             wave_mma<KS>(A0, A1, idx, L, acc);
+            idx[0] = nidx[0];
+            idx[1] = nidx[1];
             // margin: largest norm of the tile's points, column part per lane
             const float amax = wave_max(an);
             float M[4];
 #pragma unroll
             for (int ct = 0; ct < 4; ++ct) M[ct] = fmaf(P.kappa_a, amax, cm[ct]);
-            uint32_t above[4] = {0u, 0u, 0u, 0u}, um[4] = {0u, 0u, 0u, 0u};
-            tile_signs(acc, M, above, um);
-            {
-                const uint32_t live = live_rows(wl, lh);
+            // per column tile: when no row of the wave's 64 is within the
+            // margin (and all are live), the counts follow from the sign
+            // bits; otherwise the masks of certain and uncertain rows
+            uint32_t um[4];
 #pragma unroll
-                for (int ct = 0; ct < 4; ++ct) {
-                    const uint32_t sure = um[ct] & live;
-                    above[ct] &= live;
-                    pos[ct] += (uint32_t)__builtin_popcount(above[ct]);
-                    neg[ct] += (uint32_t)__builtin_popcount(sure & ~above[ct]);
-                    um[ct] = live & ~um[ct];  // uncertain rows
+            for (int ct = 0; ct < 4; ++ct) {
+                bool certain;
+                uint32_t nneg;
+                column_stats(acc, ct, M[ct], certain, nneg);
+                if (wl == 64 && __builtin_amdgcn_ballot_w64(!certain) == 0ull) {
+                    pos[ct] += 32u - nneg;
+                    neg[ct] += nneg;
+                    um[ct] = 0u;
+                } else {
+                    uint32_t above, sure;
+                    column_masks(acc, ct, M[ct], above, sure);
+                    const uint32_t live = live_rows(wl, lh);
+                    sure &= live;
+                    above &= live;
+                    pos[ct] += (uint32_t)__builtin_popcount(above);
+                    neg[ct] += (uint32_t)__builtin_popcount(sure & ~above);
+                    um[ct] = live & ~sure;  // uncertain rows
                 }
             }
             // half columns with uncertain rows (rare): one entry each,
@@ -548,9 +625,11 @@ __global__ __launch_bounds__(256, 2) void k_cull(SignParams P)
 __global__ __launch_bounds__(256) void k_block_recheck(
     const uint64_t *__restrict__ queue, const uint32_t *__restrict__ segcnt, uint32_t seg,
     const double *__restrict__ X, int64_t n, int64_t d, const double *__restrict__ Zb,
-    const double *__restrict__ UT, int64_t ldm, const uint32_t *__restrict__ lists,
-    uint32_t *__restrict__ cnt, unsigned long long *__restrict__ tally)
+    const double *__restrict__ UT, int64_t ldm, const uint32_t *__restrict__ lists_in,
+    const uint32_t *__restrict__ mode, uint32_t *__restrict__ cnt,
+    unsigned long long *__restrict__ tally)
 {
+    const uint32_t *const lists = (mode == nullptr || *mode != 0u) ? lists_in : nullptr;
     // workgroup b: the entries of queue segment b
     const uint64_t *q = queue + 2ull * (uint64_t)blockIdx.x * (uint64_t)seg;
     const uint32_t total = segcnt[blockIdx.x];
@@ -641,22 +720,37 @@ __global__ __launch_bounds__(256) void k_cull_bounds(const double *__restrict__ 
 }
 
 // Exclusive prefix of the items per query (one workgroup): items_q =
-// ceil(lcount_q / (256 rpi)) * ceil(m / 128); offs[qb] = total.
+// ceil(lcount_q / (256 rpi)) * ceil(m / 128); offs[qb] = total.  Also picks
+// the mode of the refinement's sign GEMM: lists (*mode = 1) when their
+// matrix-core work (rows padded to 64, each query's directions to tiles of
+// 128) is below list_pct percent of the dense GEMM's over every point and
+// the flat columns, dense (*mode = 0) otherwise.
 __global__ __launch_bounds__(1024) void k_worklist(const uint32_t *__restrict__ lcount,
-                                                   int64_t qb, int64_t m, int rpi,
+                                                   int64_t qb, int64_t m, int rpi, int64_t n,
+                                                   int64_t dense_cols, int list_pct,
                                                    uint32_t *__restrict__ offs,
+                                                   uint32_t *__restrict__ mode,
                                                    unsigned long long *__restrict__ pairs)
 {
     __shared__ uint32_t part[1024];
+    __shared__ unsigned long long work, lpairs;
     const int tid = threadIdx.x;
+    if (tid == 0) work = lpairs = 0ull;
     const int64_t per = (qb + 1023) / 1024;
     const int64_t q0 = tid * per, q1 = q0 + per < qb ? q0 + per : qb;
     const uint32_t nctq = (uint32_t)((m + kTN - 1) / kTN);
     const uint32_t rows = (uint32_t)(kTM * rpi);
     uint32_t s = 0;
-    for (int64_t q = q0; q < q1; ++q) s += (lcount[q] + rows - 1) / rows * nctq;
+    unsigned long long w = 0, lp = 0;
+    for (int64_t q = q0; q < q1; ++q) {
+        s += (lcount[q] + rows - 1) / rows * nctq;
+        w += (unsigned long long)((lcount[q] + 63u) / 64u) * 64ull * nctq * (unsigned long long)kTN;
+        lp += lcount[q];
+    }
     part[tid] = s;
     __syncthreads();
+    if (w) atomicAdd(&work, w);
+    if (lp) atomicAdd(&lpairs, lp);
     // inclusive scan over the 1024 partial sums
     for (int off = 1; off < 1024; off <<= 1) {
         const uint32_t v = tid >= off ? part[tid - off] : 0u;
@@ -665,26 +759,58 @@ __global__ __launch_bounds__(1024) void k_worklist(const uint32_t *__restrict__ 
         __syncthreads();
     }
     uint32_t run = tid ? part[tid - 1] : 0u;
-    unsigned long long lp = 0;
     for (int64_t q = q0; q < q1; ++q) {
         offs[q] = run;
         run += (lcount[q] + rows - 1) / rows * nctq;
-        lp += lcount[q];
     }
     if (tid == 1023) offs[qb] = part[1023];
-    if (pairs && lp) atomicAdd(pairs, lp * (unsigned long long)m);
+    if (tid == 0) {
+        const double dense = (double)((n + 63) / 64 * 64) * (double)dense_cols;
+        const bool lists = (double)work * 100.0 < dense * (double)list_pct;
+        *mode = lists ? 1u : 0u;
+        if (pairs) atomicAdd(pairs, lists ? lpairs * (unsigned long long)m
+                                          : (unsigned long long)qb * (unsigned long long)m *
+                                                (unsigned long long)n);
+    }
+}
+
+// The list-mode items as records: q | tile << 16, first list position,
+// end list position (the GEMM reads one record per item instead of searching
+// the offsets).
+__global__ __launch_bounds__(256) void k_item_table(const uint32_t *__restrict__ offs,
+                                                    const uint32_t *__restrict__ lcount,
+                                                    int64_t qb, int64_t m, int rpi,
+                                                    const uint32_t *__restrict__ mode,
+                                                    uint32_t *__restrict__ items)
+{
+    if (*mode == 0u) return;
+    const uint32_t total = offs[qb];
+    const uint32_t nctq = (uint32_t)((m + kTN - 1) / kTN);
+    const uint32_t rows = (uint32_t)(kTM * rpi);
+    for (uint32_t it = blockIdx.x * 256u + threadIdx.x; it < total; it += gridDim.x * 256u) {
+        const int32_t q = item_query(offs, (int32_t)qb, (int32_t)it);
+        const uint32_t loc = it - offs[q];
+        const uint32_t rc = loc / nctq, ct = loc - rc * nctq;
+        const uint32_t rb = rc * rows, lc = lcount[q];
+        uint32_t *r = items + 4ull * it;
+        r[0] = (uint32_t)q | (ct << 16);
+        r[1] = rb;
+        r[2] = rb + rows < lc ? rb + rows : lc;
+        r[3] = 0u;
+    }
 }
 
 // Counts start from the decided points: cnt[q][j] = base[q] (j < m), 0 for
-// the padding directions.
+// the padding directions; from zero when the refinement runs the dense GEMM.
 __global__ __launch_bounds__(256) void k_spread_base(const uint32_t *__restrict__ base,
                                                      int64_t qb, int64_t m, int64_t ldm,
+                                                     const uint32_t *__restrict__ mode,
                                                      uint32_t *__restrict__ cnt)
 {
     const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;  // (q, j, side)
     if (e >= qb * ldm * 2) return;
     const int64_t q = e / (ldm * 2), j = (e / 2) % ldm, side = e & 1;
-    cnt[e] = j < m ? base[q * 2 + side] : 0u;
+    cnt[e] = (j < m && *mode != 0u) ? base[q * 2 + side] : 0u;
 }
 
 int g_cus = 0;
@@ -780,15 +906,19 @@ hipError_t launch_sign(const SignArgs &a, hipStream_t st)
     p.lists = a.lists;
     p.lcount = a.lcount;
     p.offs = a.offs;
-    // point tiles per item: keep about four items per workgroup at least
+    p.items = a.items;
+    // point tiles per item of the dense GEMM: keep about four items per
+    // workgroup at least
     int rpi = 4;
-    if (!a.lists) {
+    {
         const int64_t nct = (p.ncols + kTN - 1) / kTN;
         while (rpi > 1 && ((a.n + (int64_t)kTM * rpi - 1) / ((int64_t)kTM * rpi)) * nct <
                               4 * (int64_t)grid)
             rpi >>= 1;
     }
     p.rpi = a.lists ? a.rpi : rpi;
+    p.rpi_dense = rpi;
+    p.mode = a.lists ? a.mode : nullptr;
     const int ks = (int)(kp / 16);
     RRS_SIGN_KS_SWITCH(ks, go_sign, p, grid, st)
     return hipGetLastError();
@@ -799,7 +929,7 @@ hipError_t launch_block_recheck(const SignArgs &a, const double *X, uint64_t *ta
 {
     const SignQueue sq = sign_queue(a, grid_size());
     hipLaunchKernelGGL(k_block_recheck, dim3(sq.nseg), dim3(256), 0, st, a.queue, sq.segcnt, sq.seg,
-                       X, a.n, a.d, a.Z, a.UT, a.ldm, a.lists, a.cnt,
+                       X, a.n, a.d, a.Z, a.UT, a.ldm, a.lists, a.mode, a.cnt,
                        (unsigned long long *)tally);
     return hipGetLastError();
 }
@@ -841,13 +971,17 @@ hipError_t launch_cull(const SignArgs &a, const CullArgs &c, hipStream_t st)
     RRS_SIGN_KS_SWITCH(ks, go_cull, p, grid_size(), st)
     e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_worklist, dim3(1), dim3(1024), 0, st, c.lcount, a.qb, a.m, a.rpi,
-                       c.offs, c.pairs);
+    hipLaunchKernelGGL(k_worklist, dim3(1), dim3(1024), 0, st, c.lcount, a.qb, a.m, a.rpi, a.n,
+                       mfma_col_pad(a.qb * a.m), c.list_pct, c.offs, c.mode, c.pairs);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_item_table, dim3(512), dim3(256), 0, st, c.offs, c.lcount, a.qb, a.m,
+                       a.rpi, c.mode, c.items);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     const int64_t tot = a.qb * a.ldm * 2;
     hipLaunchKernelGGL(k_spread_base, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st,
-                       c.base, a.qb, a.m, a.ldm, a.cnt);
+                       c.base, a.qb, a.m, a.ldm, c.mode, a.cnt);
     return hipGetLastError();
 }
 

@@ -143,3 +143,22 @@ def test_queue_overflow_recounts_exactly(monkeypatch, words):
     w.Z = Z
     monkeypatch.setenv("RRS_QUEUE_WORDS", str(words))
     _check(w)
+
+
+@pytest.mark.parametrize("pct", ["0", "1000"])
+def test_dense_or_list_choice_after_culling(monkeypatch, pct):
+    """After culling, the device picks the dense GEMM over every point or the
+    list-mode GEMM over the undecided points by their matrix-core work;
+    forcing either (RRS_LIST_PCT 0: always dense, 1000: always lists) gives
+    the same exact results."""
+    w = workloads.small("halfspace", 5000, 24, 10, 900, 9, 0.6, law="mixture", seed_cfg=48)
+    monkeypatch.setenv("RRS_LIST_PCT", pct)
+    rrs.rrs_profile_enable(True)
+    _check(w, q0=2)
+    pairs = rrs.rrs_profile_counter("gemm_pairs")
+    rrs.rrs_profile_enable(False)
+    _say("list pct", pct, "gemm pairs", pairs, "of", w.projections)
+    if pct == "0":
+        assert pairs == w.projections
+    else:
+        assert pairs < w.projections
