@@ -244,6 +244,7 @@ int job_sizes(const JobSpec &s, int64_t n, int64_t d, const Plan &p, int64_t qb,
     sz[k++] = p.cull ? (size_t)qb * 8 : 0;                      // base
     sz[k++] = p.cull ? (size_t)(qb + 1) * 4 : 0;                // offs
     sz[k++] = p.cull ? (size_t)sign_max_items(qb, n, p.m, p.rpi) * 16 : 0;  // items
+    sz[k++] = p.sign ? (size_t)qb * p.m * d * 8 : 0;            // UR (direction rows)
     return k;
 }
 
@@ -357,6 +358,7 @@ rrs_status enqueue_job(const JobSpec &s, const DataDev &D, const Plan &p, const 
     uint32_t *base = cv.take<uint32_t>(sz[23] / 4);
     uint32_t *offs = cv.take<uint32_t>(sz[24] / 4);
     uint32_t *items = cv.take<uint32_t>(sz[25] / 4);
+    double *UR = p.sign ? cv.take<double>(sz[26] / 8) : nullptr;
     const int64_t npad_pole = p.cull ? mfma_col_pad(qb) : 0;
     const double cull_angle = env_double("RRS_CULL_ANGLE", 1.5707963267948966);
     // lists when their matrix-core work is below this percent of the dense
@@ -375,7 +377,7 @@ rrs_status enqueue_job(const JobSpec &s, const DataDev &D, const Plan &p, const 
         for (int32_t l = 1; l <= r; ++l) {
             const double proj_units = (double)nb * (double)m * (double)n;
             GenArgs ga{d, m, ldm, nb, l, phi, s.seed, (uint64_t)(s.qoff + q0), pole, UT,
-                       s.first_cap ? 1 : 0, s.area_cap ? 1 : 0};
+                       s.first_cap ? 1 : 0, s.area_cap ? 1 : 0, (half && mfma && p.sign) ? UR : nullptr};
             {
                 ProfScope ps(prof, K_GEN, (double)nb * m * d, st);
                 RRS_HIP_TRY(launch_gen_dirs(ga, st));
@@ -389,7 +391,8 @@ rrs_status enqueue_job(const JobSpec &s, const DataDev &D, const Plan &p, const 
                                              B0, B1, cmarg, D.amax, nullptr, nullptr, st));
                 SignArgs sa{n,     d,     D.A0,  D.A1,   D.anorm, B0,     B1,     cmarg,
                             npad,  m,     ldm,   nb,     cnt,     queue,  qctl,   p.qcap,
-                            UT,    Zb,    nullptr, nullptr, nullptr, nullptr, nullptr, p.rpi};
+                            UT,    UR,    Zb,    nullptr, nullptr, nullptr, nullptr, nullptr,
+                            p.rpi};
                 const bool cull_l = p.cull && l >= 2 && 1.5707963267948966 * phi <= cull_angle;
                 if (cull_l) {
                     RRS_HIP_TRY(launch_mfma_dirs(p.prec, true, pole, d, 1, 1, nb, npad_pole, Zb,

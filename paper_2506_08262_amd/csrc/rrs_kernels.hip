@@ -6,8 +6,9 @@
 //                   fma chain in coordinate order; for halfspace depth the
 //                   sign counts are fused into the epilogue (no projection
 //                   matrix is stored), otherwise columns go to scratch
-//   k_select        step a3: median / MAD / MAD_+ per column by LDS radix
-//                   select on order-preserving 64-bit keys (exact)
+//   (step a3, the median / MAD / MAD_+ selects, is in rrs_select.hip for
+//                   binary64 columns and rrs_select_rc.hip for the matrix-core
+//                   forms)
 //   k_argmin_pole   step a5: first index of the minimum, strict pole update
 //
 // Layouts (all device memory):
@@ -27,89 +28,121 @@
 namespace rrs {
 
 // ---------------------------------------------------------------------------
-// a1: directions.  One lane per (query, direction); the lane writes its
-// direction straight into UT (coalesced over directions) and re-reads it for
-// the normalisation and the reflection.
+// a1: directions.  Four lanes per (query, direction): in iteration i lane t
+// of the quad draws Philox block 4 i + t of the direction and writes its
+// coordinates into UT (coalesced over directions); the quad exchanges the
+// values with shuffles so that every lane adds the squared norm, and later
+// the reflection's dot product, in coordinate order exactly as a single
+// sequential pass does; normalisation and reflection then touch each lane's
+// own coordinates.  Lanes past m compute a dummy direction and write nothing.
 // ---------------------------------------------------------------------------
+__device__ __forceinline__ Block4 shfl_block(const Block4 &b, int src)
+{
+    return Block4{(uint64_t)__shfl((long long)b.w0, src), (uint64_t)__shfl((long long)b.w1, src),
+                  (uint64_t)__shfl((long long)b.w2, src), (uint64_t)__shfl((long long)b.w3, src)};
+}
+
 __global__ __launch_bounds__(64) void k_gen_dirs(int64_t d, int64_t m, int64_t ldm, int32_t l,
                                                  double phi, uint64_t seed, uint64_t qbase,
                                                  const double *__restrict__ pole,
                                                  double *__restrict__ UT, int32_t first_cap,
-                                                 int32_t area_cap)
+                                                 int32_t area_cap, double *__restrict__ UR)
 {
-    const int64_t j = (int64_t)blockIdx.x * 64 + threadIdx.x;
+    const int lane = threadIdx.x, t = lane & 3, q4 = lane & ~3;
+    const int64_t j = (int64_t)blockIdx.x * 16 + (lane >> 2);
     const int64_t qi = blockIdx.y;
-    if (j >= m) return;
+    const bool live = j < m;  // uniform within a quad
+    const int64_t jj = live ? j : 0;
     const uint64_t q = qbase + (uint64_t)qi;
     const uint64_t ul = (uint64_t)l;
-    double *u = UT + qi * d * ldm + j;
+    double *u = UT + qi * d * ldm + jj;
+    double *ur = (UR && live) ? UR + (qi * m + jj) * d : nullptr;
 
     if (l == 1 && !first_cap) {
-        // Alg. S1: d Gaussians from word pairs (0,1), (2,3), ... then divide
-        // by the Euclidean norm.  (first_cap: refinement 1 also draws from
-        // Alg. S4, in the half-angle pi/2 cap around the initial pole e1.)
+        // Alg. S1: block b gives the Gaussians of coordinates 4 b .. 4 b + 3
+        // from word pairs (0,1), (2,3); then divide by the Euclidean norm.
+        // (first_cap: refinement 1 also draws from Alg. S4, in the half-angle
+        // pi/2 cap around the initial pole e1.)
+        const int64_t nb = (d + 3) / 4;
         double s = 0.0;
-        for (int64_t c = 0, b = 0; c < d; c += 4, ++b) {
-            const Block4 w = dir_block(seed, q, ul, (uint64_t)j, (uint64_t)b);
-            double g0, g1;
-            gauss_pair(w.w0, w.w1, g0, g1);
-            u[c * ldm] = g0;
-            s = fma(g0, g0, s);
-            if (c + 1 < d) {
-                u[(c + 1) * ldm] = g1;
-                s = fma(g1, g1, s);
+        for (int64_t i = 0; 4 * i < nb; ++i) {
+            const int64_t b = 4 * i + t;
+            double g[4] = {0.0, 0.0, 0.0, 0.0};
+            if (b < nb) {
+                const Block4 w = dir_block(seed, q, ul, (uint64_t)jj, (uint64_t)b);
+                gauss_pair(w.w0, w.w1, g[0], g[1]);
+                if (4 * b + 2 < d) gauss_pair(w.w2, w.w3, g[2], g[3]);
+#pragma unroll
+                for (int e = 0; e < 4; ++e)
+                    if (live && 4 * b + e < d) u[(4 * b + e) * ldm] = g[e];
             }
-            if (c + 2 < d) {
-                double g2, g3;
-                gauss_pair(w.w2, w.w3, g2, g3);
-                u[(c + 2) * ldm] = g2;
-                s = fma(g2, g2, s);
-                if (c + 3 < d) {
-                    u[(c + 3) * ldm] = g3;
-                    s = fma(g3, g3, s);
+#pragma unroll
+            for (int tt = 0; tt < 4; ++tt)
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const double v = __shfl(g[e], q4 + tt);
+                    if (4 * (4 * i + tt) + e < d) s = fma(v, v, s);
                 }
-            }
         }
         const double nrm = sqrt(s);
-        for (int64_t c = 0; c < d; ++c) u[c * ldm] = u[c * ldm] / nrm;
+        for (int64_t b = t; b < nb; b += 4)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int64_t c = 4 * b + e;
+                if (live && c < d) {
+                    const double v = u[c * ldm] / nrm;
+                    u[c * ldm] = v;
+                    if (ur) ur[c] = v;
+                }
+            }
         return;
     }
 
-    // Alg. S4: polar angle (pi/2) * U * phi from word 0, tangent Gaussians
-    // h_1..h_{d-1} from word pairs (1,2), (3,4), ...; pair 2k uses words
-    // 4k+1, 4k+2 of block k and pair 2k+1 uses word 4k+3 of block k and word
-    // 4k+4 (= word 0 of block k+1).
-    Block4 a = dir_block(seed, q, ul, (uint64_t)j, 0);
+    // Alg. S4: polar angle (pi/2) * U * phi from word 0 of block 0, tangent
+    // Gaussians h_1..h_{d-1} from word pairs (1,2), (3,4), ...: block b gives
+    // coordinates 4 b + 1, 4 b + 2 from its words 1, 2 and 4 b + 3, 4 b + 4
+    // from its word 3 and word 0 of block b + 1.  Lane t draws block
+    // 4 i + t + 1 in iteration i: its own next block, lane t + 1's block, and
+    // (lane 3) lane 0's block of the next iteration.
+    const Block4 b0 = dir_block(seed, q, ul, (uint64_t)jj, 0);
     double st, ct;
     if (area_cap)
-        area_cap_angle(uniform_open(a.w0), phi, d, st, ct);  // area-uniform in the cap
+        area_cap_angle(uniform_open(b0.w0), phi, d, st, ct);  // area-uniform in the cap
     else
-        sincos_halfpi(uniform_open(a.w0) * phi, st, ct);
+        sincos_halfpi(uniform_open(b0.w0) * phi, st, ct);
+    const int64_t nbk = (d - 1 + 3) / 4;  // blocks holding tangent coordinates
     double s = 0.0;
-    for (int64_t c = 1, b = 0;; c += 4, ++b) {
-        if (c > d - 1) break;
-        double h0, h1;
-        gauss_pair(a.w1, a.w2, h0, h1);
-        u[c * ldm] = h0;
-        s = fma(h0, h0, s);
-        if (c + 1 <= d - 1) {
-            u[(c + 1) * ldm] = h1;
-            s = fma(h1, h1, s);
+    Block4 carry = b0;
+    for (int64_t i = 0; 4 * i < nbk; ++i) {
+        const int64_t b = 4 * i + t;
+        const Block4 nxt = dir_block(seed, q, ul, (uint64_t)jj, (uint64_t)(b + 1));
+        const Block4 fromprev = shfl_block(nxt, q4 + ((t + 3) & 3));
+        const Block4 cur = t == 0 ? carry : fromprev;
+        carry = shfl_block(nxt, q4 + 3);
+        double h[4] = {0.0, 0.0, 0.0, 0.0};
+        if (b < nbk) {
+            const int64_t c = 1 + 4 * b;
+            gauss_pair(cur.w1, cur.w2, h[0], h[1]);
+            if (c + 2 <= d - 1) gauss_pair(cur.w3, nxt.w0, h[2], h[3]);
+#pragma unroll
+            for (int e = 0; e < 4; ++e)
+                if (live && c + e <= d - 1) u[(c + e) * ldm] = h[e];
         }
-        if (c + 2 > d - 1) break;
-        const Block4 nb = dir_block(seed, q, ul, (uint64_t)j, (uint64_t)(b + 1));
-        double h2, h3;
-        gauss_pair(a.w3, nb.w0, h2, h3);
-        u[(c + 2) * ldm] = h2;
-        s = fma(h2, h2, s);
-        if (c + 3 <= d - 1) {
-            u[(c + 3) * ldm] = h3;
-            s = fma(h3, h3, s);
-        }
-        a = nb;
+#pragma unroll
+        for (int tt = 0; tt < 4; ++tt)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const double v = __shfl(h[e], q4 + tt);
+                if (1 + 4 * (4 * i + tt) + e <= d - 1) s = fma(v, v, s);
+            }
     }
     const double nrm = sqrt(s);
-    for (int64_t c = 1; c < d; ++c) u[c * ldm] = st * (u[c * ldm] / nrm);
+    for (int64_t b = t; b < nbk; b += 4)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int64_t c = 1 + 4 * b + e;
+            if (live && c <= d - 1) u[c * ldm] = st * (u[c * ldm] / nrm);
+        }
     const double v0 = ct;
 
     // Householder reflection taking e1 to the pole p: w = e1 - p,
@@ -119,14 +152,51 @@ __global__ __launch_bounds__(64) void k_gen_dirs(int64_t d, int64_t m, int64_t l
     double ww = am * am;
     for (int64_t c = 1; c < d; ++c) ww = fma(p[c], p[c], ww);
     if (ww == 0.0) {
-        u[0] = v0;
+        if (live && t == 0) u[0] = v0;
+        if (ur) {
+            if (t == 0) ur[0] = v0;
+            for (int64_t b = t; b < nbk; b += 4)
+                for (int e = 0; e < 4; ++e) {
+                    const int64_t c = 1 + 4 * b + e;
+                    if (c <= d - 1) ur[c] = u[c * ldm];
+                }
+        }
         return;
     }
     double wv = am * v0;
-    for (int64_t c = 1; c < d; ++c) wv = fma(-p[c], u[c * ldm], wv);
+    for (int64_t i = 0; 4 * i < nbk; ++i) {
+        const int64_t b = 4 * i + t;
+        double v[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int64_t c = 1 + 4 * b + e;
+            if (live && b < nbk && c <= d - 1) v[e] = u[c * ldm];
+        }
+#pragma unroll
+        for (int tt = 0; tt < 4; ++tt)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const double x = __shfl(v[e], q4 + tt);
+                const int64_t c = 1 + 4 * (4 * i + tt) + e;
+                if (c <= d - 1) wv = fma(-p[c], x, wv);
+            }
+    }
     const double beta = (2.0 * wv) / ww;
-    u[0] = fma(-beta, am, v0);
-    for (int64_t c = 1; c < d; ++c) u[c * ldm] = fma(beta, p[c], u[c * ldm]);
+    if (live && t == 0) {
+        const double u0 = fma(-beta, am, v0);
+        u[0] = u0;
+        if (ur) ur[0] = u0;
+    }
+    for (int64_t b = t; b < nbk; b += 4)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int64_t c = 1 + 4 * b + e;
+            if (live && c <= d - 1) {
+                const double x = fma(beta, p[c], u[c * ldm]);
+                u[c * ldm] = x;
+                if (ur) ur[c] = x;
+            }
+        }
 }
 
 // ---------------------------------------------------------------------------
@@ -241,247 +311,6 @@ __global__ __launch_bounds__(256) void k_proj_f64(
             if (j0 + jj < m && sum) atomicAdd(&cnt[(qi * ldm + j0 + jj) * 2 + w], sum);
         }
     }
-}
-
-// ---------------------------------------------------------------------------
-// a3 for projection / APD: exact order statistics of one column by radix
-// select over order-preserving 64-bit keys, 8 bits per pass, stopping as soon
-// as the selected bucket holds at most kCand elements (they are then ranked
-// directly).  The column sits in LDS when it fits, otherwise it is read from
-// the scratch buffer on every pass.
-// ---------------------------------------------------------------------------
-constexpr int kSelThreads = 512;
-constexpr int kCand = 64;
-
-struct SelShared {
-    uint32_t hist[256];
-    uint64_t cand[kCand];
-    uint32_t ncand;
-    uint32_t sel_bucket, sel_before, sel_count;
-    uint64_t result;
-    uint64_t minkey;
-    uint32_t count;
-};
-
-enum { KEY_T = 0, KEY_ABSDEV = 1, KEY_POSDEV = 2 };
-
-template <bool LDS>
-__device__ __forceinline__ double col_load(const double *g, const double *s, int64_t i)
-{
-    return LDS ? s[i] : g[i];
-}
-
-template <int MODE>
-__device__ __forceinline__ bool make_key(double t, double med, uint64_t &key)
-{
-    if (MODE == KEY_T) {
-        key = order_key(t);
-        return true;
-    } else if (MODE == KEY_ABSDEV) {
-        key = order_key(fabs(t - med));
-        return true;
-    } else {
-        const double dv = t - med;
-        key = order_key(dv);
-        return dv > 0.0;
-    }
-}
-
-__device__ __forceinline__ void block_sync() { __syncthreads(); }
-
-// Key of the k-th smallest (0-based) included element.
-template <int MODE, bool LDS>
-__device__ uint64_t select_kth(const double *g, const double *s, int64_t n, double med,
-                               uint64_t k, SelShared &sh)
-{
-    const int tid = threadIdx.x;
-    const int lane = tid & 63;
-    uint64_t prefix = 0, pmask = 0;
-    for (int shift = 56; shift >= 0; shift -= 8) {
-        for (int b = tid; b < 256; b += kSelThreads) sh.hist[b] = 0;
-        block_sync();
-        for (int64_t i0 = 0; i0 < n; i0 += kSelThreads) {
-            const int64_t i = i0 + tid;
-            uint64_t key = 0;
-            bool act = false;
-            if (i < n) {
-                act = make_key<MODE>(col_load<LDS>(g, s, i), med, key);
-                act = act && ((key & pmask) == prefix);
-            }
-            const uint32_t bucket = (uint32_t)(key >> shift) & 255u;
-            if (shift == 56) {
-                // first pass: few distinct buckets, aggregate per wave
-                uint64_t am = __ballot(act);
-                while (am) {
-                    const int leader = __ffsll((long long)am) - 1;
-                    const uint32_t lb = (uint32_t)__shfl((int)bucket, leader);
-                    const uint64_t same = __ballot(act && bucket == lb);
-                    if (lane == leader) atomicAdd(&sh.hist[lb], (uint32_t)__popcll(same));
-                    if (bucket == lb) act = false;
-                    am &= ~same;
-                }
-            } else if (act) {
-                atomicAdd(&sh.hist[bucket], 1u);
-            }
-        }
-        block_sync();
-        if (tid < 64) {
-            const uint32_t h0 = sh.hist[4 * lane], h1 = sh.hist[4 * lane + 1];
-            const uint32_t h2 = sh.hist[4 * lane + 2], h3 = sh.hist[4 * lane + 3];
-            const uint32_t tot = h0 + h1 + h2 + h3;
-            uint32_t incl = tot;
-            for (int off = 1; off < 64; off <<= 1) {
-                const uint32_t v = (uint32_t)__shfl_up((int)incl, off);
-                if (lane >= off) incl += v;
-            }
-            const uint64_t excl = incl - tot;
-            if (excl <= k && k < (uint64_t)incl) {
-                uint64_t c = excl;
-                uint32_t sel = 0, cntb = 0;
-                const uint32_t hs[4] = {h0, h1, h2, h3};
-                for (int b = 0; b < 4; ++b) {
-                    if (k < c + hs[b]) {
-                        sel = 4 * lane + b;
-                        cntb = hs[b];
-                        break;
-                    }
-                    c += hs[b];
-                }
-                sh.sel_bucket = sel;
-                sh.sel_before = (uint32_t)c;
-                sh.sel_count = cntb;
-            }
-        }
-        block_sync();
-        const uint32_t selb = sh.sel_bucket;
-        const uint32_t cntb = sh.sel_count;
-        k -= sh.sel_before;
-        prefix |= (uint64_t)selb << shift;
-        pmask |= 0xFFull << shift;
-        if (shift == 0) break;
-        if (cntb <= (uint32_t)kCand) {
-            if (tid == 0) sh.ncand = 0;
-            block_sync();
-            for (int64_t i0 = 0; i0 < n; i0 += kSelThreads) {
-                const int64_t i = i0 + tid;
-                if (i < n) {
-                    uint64_t key;
-                    bool act = make_key<MODE>(col_load<LDS>(g, s, i), med, key);
-                    if (act && (key & pmask) == prefix) {
-                        const uint32_t pos = atomicAdd(&sh.ncand, 1u);
-                        if (pos < (uint32_t)kCand) sh.cand[pos] = key;
-                    }
-                }
-            }
-            block_sync();
-            if (tid < 64) {
-                const uint32_t nc = sh.ncand < (uint32_t)kCand ? sh.ncand : (uint32_t)kCand;
-                if ((uint32_t)lane < nc) {
-                    const uint64_t mine = sh.cand[lane];
-                    uint32_t lt = 0, le = 0;
-                    for (uint32_t x = 0; x < nc; ++x) {
-                        const uint64_t o = sh.cand[x];
-                        lt += (o < mine);
-                        le += (o <= mine);
-                    }
-                    if (lt <= k && k < le) sh.result = mine;
-                }
-            }
-            block_sync();
-            const uint64_t r = sh.result;
-            block_sync();
-            return r;
-        }
-    }
-    block_sync();
-    return prefix;
-}
-
-// Given the key A of the k-th smallest included element, the key of the
-// (k+1)-th: A again if more than k+1 included keys are <= A, else the
-// smallest included key above A.
-template <int MODE, bool LDS>
-__device__ uint64_t select_next(const double *g, const double *s, int64_t n, double med,
-                                uint64_t k, uint64_t A, SelShared &sh)
-{
-    const int tid = threadIdx.x;
-    if (tid == 0) {
-        sh.count = 0;
-        sh.minkey = ~0ull;
-    }
-    block_sync();
-    uint32_t le = 0;
-    uint64_t mn = ~0ull;
-    for (int64_t i = tid; i < n; i += kSelThreads) {
-        uint64_t key;
-        if (make_key<MODE>(col_load<LDS>(g, s, i), med, key)) {
-            le += (key <= A);
-            if (key > A && key < mn) mn = key;
-        }
-    }
-    if (le) atomicAdd(&sh.count, le);
-    if (mn != ~0ull) atomicMin((unsigned long long *)&sh.minkey, (unsigned long long)mn);
-    block_sync();
-    const uint64_t res = ((uint64_t)sh.count >= k + 2) ? A : sh.minkey;
-    block_sync();
-    return res;
-}
-
-template <int MODE, bool LDS>
-__device__ double median_of(const double *g, const double *s, int64_t cnt, int64_t n,
-                            double med, SelShared &sh)
-{
-    if (cnt & 1) {
-        return key_value(select_kth<MODE, LDS>(g, s, n, med, (uint64_t)(cnt / 2), sh));
-    }
-    const uint64_t k = (uint64_t)(cnt / 2 - 1);
-    const uint64_t A = select_kth<MODE, LDS>(g, s, n, med, k, sh);
-    const uint64_t B = select_next<MODE, LDS>(g, s, n, med, k, A, sh);
-    return (key_value(A) + key_value(B)) * 0.5;
-}
-
-template <int NOTION, bool LDS>
-__global__ __launch_bounds__(kSelThreads) void k_select(const double *__restrict__ T, int64_t n,
-                                                        int64_t m, int64_t ldm,
-                                                        double *__restrict__ Dj)
-{
-    extern __shared__ double scol[];
-    __shared__ SelShared sh;
-    const int64_t j = blockIdx.x;
-    const int64_t qi = blockIdx.y;
-    const double *g = T + (qi * m + j) * n;
-    if (LDS) {
-        for (int64_t i = threadIdx.x; i < n; i += kSelThreads) scol[i] = g[i];
-        block_sync();
-    }
-    const double med = median_of<KEY_T, LDS>(g, scol, n, n, 0.0, sh);
-    double D;
-    if (NOTION == NOTION_PROJECTION) {
-        const double mad = median_of<KEY_ABSDEV, LDS>(g, scol, n, n, med, sh);
-        if (mad == 0.0)
-            D = (med == 0.0) ? 1.0 : 0.0;
-        else
-            D = 1.0 / (1.0 + fabs(med) / mad);
-    } else {
-        // APD: count the strictly positive deviations, then their median
-        if (threadIdx.x == 0) sh.count = 0;
-        block_sync();
-        uint32_t np = 0;
-        for (int64_t i = threadIdx.x; i < n; i += kSelThreads)
-            np += (col_load<LDS>(g, scol, i) - med > 0.0);
-        if (np) atomicAdd(&sh.count, np);
-        block_sync();
-        const int64_t npos = sh.count;
-        block_sync();
-        const double num = (med < 0.0) ? -med : 0.0;
-        if (npos == 0) {
-            D = (num == 0.0) ? 1.0 : 0.0;
-        } else {
-            const double madp = median_of<KEY_POSDEV, LDS>(g, scol, npos, n, med, sh);
-            D = 1.0 / (1.0 + num / madp);
-        }
-    }
-    if (threadIdx.x == 0) Dj[qi * ldm + j] = D;
 }
 
 // ---------------------------------------------------------------------------
@@ -614,9 +443,9 @@ static inline unsigned ceil_div(int64_t a, int64_t b) { return (unsigned)((a + b
 
 hipError_t launch_gen_dirs(const GenArgs &a, hipStream_t st)
 {
-    dim3 grid(ceil_div(a.m, 64), (unsigned)a.qb);
+    dim3 grid(ceil_div(a.m, 16), (unsigned)a.qb);
     hipLaunchKernelGGL(k_gen_dirs, grid, dim3(64), 0, st, a.d, a.m, a.ldm, a.l, a.phi, a.seed,
-                       a.qbase, a.pole, a.UT, a.first_cap, a.area_cap);
+                       a.qbase, a.pole, a.UT, a.first_cap, a.area_cap, a.UR);
     return hipGetLastError();
 }
 
@@ -661,38 +490,6 @@ hipError_t launch_proj_f64(const ProjArgs &a, bool count_mode, hipStream_t st)
         hipLaunchKernelGGL((k_proj_f64<JT, false>), grid, dim3(256), 0, st, a.XT, a.ldx, a.n,
                            a.d, a.Z, a.UT, a.ldm, a.m, a.cnt, a.T, per, a.only_if);
     return hipGetLastError();
-}
-
-int64_t select_lds_max_n(int device)
-{
-    hipDeviceProp_t prop;
-    if (hipGetDeviceProperties(&prop, device) != hipSuccess) return 0;
-    const int64_t avail = (int64_t)prop.sharedMemPerBlock - (int64_t)sizeof(SelShared) - 1024;
-    return avail > 0 ? avail / 8 : 0;
-}
-
-template <int NOTION>
-static hipError_t launch_select_t(const SelectArgs &a, bool lds, hipStream_t st)
-{
-    dim3 grid((unsigned)a.m, (unsigned)a.qb);
-    if (lds) {
-        const size_t bytes = (size_t)a.n * sizeof(double);
-        hipError_t e = hipFuncSetAttribute((const void *)k_select<NOTION, true>,
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
-        if (e != hipSuccess) return e;
-        hipLaunchKernelGGL((k_select<NOTION, true>), grid, dim3(kSelThreads), bytes, st, a.T, a.n,
-                           a.m, a.ldm, a.Dj);
-    } else {
-        hipLaunchKernelGGL((k_select<NOTION, false>), grid, dim3(kSelThreads), 0, st, a.T, a.n,
-                           a.m, a.ldm, a.Dj);
-    }
-    return hipGetLastError();
-}
-
-hipError_t launch_select(const SelectArgs &a, int notion, bool lds, hipStream_t st)
-{
-    if (notion == NOTION_PROJECTION) return launch_select_t<NOTION_PROJECTION>(a, lds, st);
-    return launch_select_t<NOTION_APD>(a, lds, st);
 }
 
 hipError_t launch_argmin(const ArgminArgs &a, bool half, hipStream_t st)

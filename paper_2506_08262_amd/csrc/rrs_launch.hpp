@@ -26,6 +26,7 @@ struct GenArgs {
     double *UT;
     int32_t first_cap = 0;  // 1: refinement 1 draws from Alg. S4's cap (phi = 1) too
     int32_t area_cap = 0;   // 1: cap directions uniform in area instead of in angle
+    double *UR = nullptr;   // optional [qb][m][d] copy, one contiguous row per direction
 };
 
 struct ProjArgs {
@@ -98,8 +99,6 @@ hipError_t launch_transpose(const double *X, int64_t n, int64_t d, int64_t ldx, 
                             hipStream_t st);
 hipError_t launch_fill_u32(uint32_t *p, int64_t count, uint32_t v, hipStream_t st);
 hipError_t launch_proj_f64(const ProjArgs &a, bool count_mode, hipStream_t st);
-int64_t select_lds_max_n(int device);
-hipError_t launch_select(const SelectArgs &a, int notion, bool lds, hipStream_t st);
 int64_t select_reg_max_n();
 hipError_t launch_select_reg(const SelectArgs &a, int notion, hipStream_t st);
 hipError_t launch_select_stream(const SelectArgs &a, int notion, hipStream_t st);
@@ -142,7 +141,8 @@ struct SignArgs {
     uint64_t *queue;           // qcap words: recheck entries
     uint32_t *qcount;          // zeroed by the caller; kSignQueueOverflow on overflow
     uint64_t qcap;
-    const double *UT;          // [qb][d][ldm] binary64 directions (cull bounds, recheck)
+    const double *UT;          // [qb][d][ldm] binary64 directions (cull bounds)
+    const double *UR;          // [qb][m][d] the same, a row per direction (recheck)
     const double *Z;           // [qb][d]
     // list mode: the undecided points of each query (null: every point), and
     // the items of the list-mode GEMM (four words each: q | tile << 16, first

@@ -617,7 +617,7 @@ __global__ __launch_bounds__(256, 2) void k_cull(SignParams P)
 // uncertain rows (bit 16 rt + r: row 32 rt + 8 (r / 4) + 4 h + r % 4 of the
 // wave tile), nearly always a single row.  One lane per entry: each masked
 // row gets the binary64 recipe value (the recipe's fma chain over the point's
-// row) and both counts from it; the other rows of the half column were
+// row and the direction's row, both contiguous) and both counts from it; the other rows of the half column were
 // counted by the sign GEMM.  Workgroup b takes the entries of queue segment
 // b (those of one wave of the sign GEMM, in the order it met them), so a
 // wave's lanes mostly share the query and read nearby directions.  Rows index
@@ -625,8 +625,8 @@ __global__ __launch_bounds__(256, 2) void k_cull(SignParams P)
 __global__ __launch_bounds__(256) void k_block_recheck(
     const uint64_t *__restrict__ queue, const uint32_t *__restrict__ segcnt, uint32_t seg,
     const double *__restrict__ X, int64_t n, int64_t d, const double *__restrict__ Zb,
-    const double *__restrict__ UT, int64_t ldm, const uint32_t *__restrict__ lists_in,
-    const uint32_t *__restrict__ mode, uint32_t *__restrict__ cnt,
+    const double *__restrict__ UR, int64_t m, const uint32_t *__restrict__ lists_in,
+    const uint32_t *__restrict__ mode, int64_t ldm, uint32_t *__restrict__ cnt,
     unsigned long long *__restrict__ tally)
 {
     const uint32_t *const lists = (mode == nullptr || *mode != 0u) ? lists_in : nullptr;
@@ -642,7 +642,7 @@ __global__ __launch_bounds__(256) void k_block_recheck(
         const uint32_t lo = (uint32_t)(w & 0xFFFFFFFFu);
         const int64_t r0 = (int64_t)(lo & ~63u) + 4 * (int64_t)(lo & 1u);
         const double *z = Zb + qi * d;
-        const double *u = UT + qi * d * ldm + j;
+        const double *u = UR + (qi * m + j) * d;
         uint32_t le = 0, ge = 0;
         for (uint32_t bits = mask; bits; bits &= bits - 1u) {
             const int k = __builtin_ctz(bits);
@@ -651,7 +651,7 @@ __global__ __launch_bounds__(256) void k_block_recheck(
             const double *x = X + i * d;
             double t = 0.0;
 #pragma unroll 4
-            for (int64_t c = 0; c < d; ++c) t = fma(x[c] - z[c], u[c * ldm], t);
+            for (int64_t c = 0; c < d; ++c) t = fma(x[c] - z[c], u[c], t);
             le += t <= 0.0 ? 1u : 0u;
             ge += t >= 0.0 ? 1u : 0u;
         }
@@ -929,7 +929,7 @@ hipError_t launch_block_recheck(const SignArgs &a, const double *X, uint64_t *ta
 {
     const SignQueue sq = sign_queue(a, grid_size());
     hipLaunchKernelGGL(k_block_recheck, dim3(sq.nseg), dim3(256), 0, st, a.queue, sq.segcnt, sq.seg,
-                       X, a.n, a.d, a.Z, a.UT, a.ldm, a.lists, a.mode, a.cnt,
+                       X, a.n, a.d, a.Z, a.UR, a.m, a.lists, a.mode, a.ldm, a.cnt,
                        (unsigned long long *)tally);
     return hipGetLastError();
 }
