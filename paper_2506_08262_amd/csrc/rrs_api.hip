@@ -292,6 +292,9 @@ rrs_status run(int notion, const double *X, int64_t n, int64_t d, const double *
         return RRS_OK;
     }
     RRS_HIP_TRY(rrs::data_prepare(D, data_mem, plan.prec, st));
+    // per-point bounds for heavy-tailed data (the graph path above keeps the
+    // column bound: its preparation runs inside the captured graph)
+    if (notion != rrs::NOTION_HALFSPACE) RRS_HIP_TRY(rrs::data_point_bounds(D, st));
     uint32_t *pstats[kMaxParts] = {};
     rrs_status es = RRS_OK;
     if (!split) {

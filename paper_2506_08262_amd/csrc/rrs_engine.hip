@@ -170,6 +170,22 @@ hipError_t data_prepare(DataDev &D, void *mem, int prec, hipStream_t st)
     return launch_mfma_prep(prec, D.X, n, d, D.xbar, D.A0, D.A1, D.anorm, D.amax, st);
 }
 
+hipError_t data_point_bounds(DataDev &D, hipStream_t st)
+{
+    D.pp = false;
+    if (D.prec < 0 || D.prec == MFMA_F32_PLAIN || !D.amax) return hipSuccess;
+    const double force = env_double("RRS_POINT_BOUNDS", -1.0);
+    if (force >= 0.0) {
+        D.pp = force > 0.0;
+        return hipSuccess;
+    }
+    uint32_t w[4] = {0u, 0u, 0u, 0u};
+    hipError_t e = hipMemcpyAsync(w, D.amax, sizeof(w), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e == hipSuccess) D.pp = w[1] != 0u;
+    return e;
+}
+
 int job_mfma_prec(int precision)
 {
     switch (precision) {
@@ -456,14 +472,15 @@ rrs_status enqueue_job(const JobSpec &s, const DataDev &D, const Plan &p, const 
             } else if (mfma) {
                 // projection / APD from binary32 projections on the matrix cores
                 RRS_HIP_TRY(launch_mfma_dirs(p.prec, false, UT, d, m, ldm, nb * m, npad, Zb,
-                                             D.xbar, B0, B1, nullptr, D.amax, cq, eq, st));
+                                             D.xbar, B0, B1, nullptr, D.amax, cq, eq, st, D.pp));
                 {
                     ProfScope ps(prof, K_MFMA, proj_units, st);
                     RRS_HIP_TRY(launch_mfma_store(p.prec, D.A0, D.A1, n, d, B0, B1, m, nb * m,
                                                   npad, S32, st));
                 }
                 SelectRcArgs ra{S32, n, m, ldm, nb, cq, eq, D.X, d, Zb, UT, Dj,
-                                profiling ? stats : nullptr};
+                                profiling ? stats : nullptr, D.anorm, D.pp,
+                                mfma_point_alpha(p.prec, d)};
                 ProfScope ps(prof, K_SELECT, proj_units, st);
                 if (profiling) prof->sel_total += 2.0 * (double)(nb * m);
                 RRS_HIP_TRY(launch_select_rc(ra, s.notion, p.prec != MFMA_F32_PLAIN, st));

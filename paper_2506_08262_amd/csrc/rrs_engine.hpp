@@ -92,7 +92,8 @@ struct DataDev {
     double *xbar = nullptr;      // [d] column means
     void *A0 = nullptr, *A1 = nullptr;  // [n][kp] centred operands
     float *anorm = nullptr;      // [n] norm bounds of the centred points
-    float *amax = nullptr;       // largest of them (one value)
+    float *amax = nullptr;       // largest of them, flag, sum of squares (16 words)
+    bool pp = false;             // stored-projection selects with per-point bounds
 };
 
 // Bytes of the prepared data beyond X itself: XT, plus the operands of one
@@ -101,6 +102,9 @@ size_t data_bytes(int64_t n, int64_t d, int prec);
 // Carves the prepared arrays from mem (data_bytes(n, d, prec) bytes) and
 // enqueues their preparation from D.X on st.
 hipError_t data_prepare(DataDev &D, void *mem, int prec, hipStream_t st);
+// Whether the stored-projection selects take per-point bounds on this data
+// (waits for the preparation; RRS_POINT_BOUNDS = 0 / 1 forces it off / on).
+hipError_t data_point_bounds(DataDev &D, hipStream_t st);
 
 // ---------------------------------------------------------------------------
 // One job: nq queries of one notion on a data set.

@@ -80,6 +80,11 @@ struct SelectRcArgs {
     const double *UT;          // [qb][d][ldm]
     double *Dj;
     uint32_t *stats;
+    // per-point bounds (heavy-tailed data; eq then holds the column part and
+    // point i adds alpha anorm[i])
+    const float *anorm;
+    bool pp;
+    double alpha;
 };
 
 struct ArgminArgs {
@@ -108,12 +113,21 @@ int64_t mfma_kpad(int prec, int64_t d);
 size_t mfma_elem_bytes(int prec);
 int mfma_terms(int prec);
 void mfma_margins(int prec, int64_t d, int64_t kp, double *kappa, double *canon);
+// amax: 16 words; [0] the largest norm bound, [1] the per-point-bound flag
+// (set when that norm exceeds 4x the root mean square norm), [2..3] the sum
+// of squared norms (binary64).
 hipError_t launch_mfma_prep(int prec, const double *X, int64_t n, int64_t d, double *xbar,
                             void *A0, void *A1, float *anorm, float *amax, hipStream_t st);
+// Per-point factor of the stored-projection bound: point i's bound is
+// alpha anorm[i] plus the column part.
+double mfma_point_alpha(int prec, int64_t d);
+// pp (stored projections): eq holds only the column part of per-point
+// bounds (alpha anorm[i] + eq[J], alpha = mfma_point_alpha).
 hipError_t launch_mfma_dirs(int prec, bool fold, const double *UT, int64_t d, int64_t m,
                             int64_t ldm, int64_t ncols, int64_t npad, const double *Zb,
                             const double *xbar, void *B0, void *B1, float *cmarg,
-                            const float *amax, double *cq, double *eq, hipStream_t st);
+                            const float *amax, double *cq, double *eq, hipStream_t st,
+                            bool pp = false);
 hipError_t launch_mfma_store(int prec, const void *A0, const void *A1, int64_t n, int64_t d,
                              const void *B0, const void *B1, int64_t m, int64_t ncols,
                              int64_t npad, float *S, hipStream_t st);

@@ -72,31 +72,44 @@ __global__ __launch_bounds__(256) void k_prep_data(const double *__restrict__ X,
                                                    float *__restrict__ amax)
 {
     const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (i >= n) return;
-    // column d (and d + 1 for BF16) multiplies the folded centring term
-    const int64_t nfold = PREC == MFMA_BF16 ? 2 : 1;
     double ss = 0.0;
-    for (int64_t c = 0; c < kp; ++c) {
-        double a = 0.0;
-        if (c < d) {
-            a = X[i * d + c] - xbar[c];
-            ss = fma(a, a, ss);
-        } else if (c < d + nfold) {
-            a = 1.0;
+    if (i < n) {
+        // column d (and d + 1 for BF16) multiplies the folded centring term
+        const int64_t nfold = PREC == MFMA_BF16 ? 2 : 1;
+        for (int64_t c = 0; c < kp; ++c) {
+            double a = 0.0;
+            if (c < d) {
+                a = X[i * d + c] - xbar[c];
+                ss = fma(a, a, ss);
+            } else if (c < d + nfold) {
+                a = 1.0;
+            }
+            if (PREC == MFMA_BF16) {
+                const __bf16 h = to_bf16(a);
+                ((__bf16 *)A0)[i * kp + c] = h;
+                ((__bf16 *)A1)[i * kp + c] = c < d ? to_bf16(a - from_bf16(h)) : (__bf16)0.0f;
+            } else {
+                ((float *)A0)[i * kp + c] = (float)a;
+            }
         }
-        if (PREC == MFMA_BF16) {
-            const __bf16 h = to_bf16(a);
-            ((__bf16 *)A0)[i * kp + c] = h;
-            ((__bf16 *)A1)[i * kp + c] = c < d ? to_bf16(a - from_bf16(h)) : (__bf16)0.0f;
-        } else {
-            ((float *)A0)[i * kp + c] = (float)a;
-        }
+        // upper bound of the norm, rounded up to binary32
+        const float nf = (float)sqrt(ss);
+        anorm[i] = nf * (1.0f + 1e-6f);
+        // largest norm bound (non-negative floats order like their bit patterns)
+        atomicMax((int *)amax, __float_as_int(anorm[i]));
     }
-    // upper bound of the norm, rounded up to binary32
-    const float nf = (float)sqrt(ss);
-    anorm[i] = nf * (1.0f + 1e-6f);
-    // largest norm bound (non-negative floats order like their bit patterns)
-    atomicMax((int *)amax, __float_as_int(anorm[i]));
+    // sum of the squared norms: per wave (every lane takes part), then one atomic
+    double w = ss;
+    for (int o = 32; o > 0; o >>= 1) w += __shfl_xor(w, o);
+    if ((threadIdx.x & 63) == 0 && w != 0.0) atomicAdd((double *)(amax + 2), w);
+}
+
+// Per-point bounds for heavy-tailed data: the flag is set when the largest
+// norm exceeds 4x the root mean square norm (Gaussian-like data stays below).
+__global__ void k_point_flag(float *__restrict__ amax, int64_t n)
+{
+    const double rms = sqrt(*(const double *)(amax + 2) / (double)n);
+    ((uint32_t *)amax)[1] = (double)amax[0] > 4.0 * rms ? 1u : 0u;
 }
 
 // Per refinement: the directions (binary64, [q][d][ldm] in UT) in the GEMM's
@@ -117,7 +130,7 @@ __global__ __launch_bounds__(64) void k_prep_dirs(const double *__restrict__ UT,
                                                   float *__restrict__ cmarg,
                                                   const float *__restrict__ amax,
                                                   double *__restrict__ cq,
-                                                  double *__restrict__ eq)
+                                                  double *__restrict__ eq, int pp)
 {
     const int64_t J = (int64_t)blockIdx.x * 64 + threadIdx.x;
     if (J >= npad) return;
@@ -193,9 +206,15 @@ __global__ __launch_bounds__(64) void k_prep_dirs(const double *__restrict__ UT,
         const double mc = kappa * fabs(cj) + canon * sqrt(bn) * 1.000001 + 1e-300;
         cmarg[J] = (float)mc * (1.0f + 1e-6f);
     } else {
-        const double am = (double)*amax;
         cq[J] = cj;
-        eq[J] = (kappa * am + canon * (am + 2.0 * sqrt(bn) * 1.000001)) * 1.000001;
+        if (pp) {
+            // per-point bounds: the column part only (point i adds
+            // mfma_point_alpha * anorm[i])
+            eq[J] = canon * 2.0 * sqrt(bn) * 1.000001 * 1.000002;
+        } else {
+            const double am = (double)*amax;
+            eq[J] = (kappa * am + canon * (am + 2.0 * sqrt(bn) * 1.000001)) * 1.000001;
+        }
     }
 }
 
@@ -922,7 +941,7 @@ int mfma_terms(int prec) { return prec == MFMA_BF16 ? 2 : 1; }
 hipError_t launch_mfma_prep(int prec, const double *X, int64_t n, int64_t d, double *xbar,
                             void *A0, void *A1, float *anorm, float *amax, hipStream_t st)
 {
-    hipError_t e = launch_fill_u32((uint32_t *)amax, 1, 0u, st);
+    hipError_t e = launch_fill_u32((uint32_t *)amax, 4, 0u, st);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_col_mean, dim3((unsigned)d), dim3(256), 0, st, X, n, d, xbar);
     e = hipGetLastError();
@@ -935,13 +954,24 @@ hipError_t launch_mfma_prep(int prec, const double *X, int64_t n, int64_t d, dou
     else
         hipLaunchKernelGGL(k_prep_data<MFMA_F32>, grid, dim3(256), 0, st, X, n, d, kp, xbar, A0,
                            A1, anorm, amax);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_point_flag, dim3(1), dim3(1), 0, st, amax, n);
     return hipGetLastError();
+}
+
+double mfma_point_alpha(int prec, int64_t d)
+{
+    double kappa, canon;
+    mfma_margins(prec, d, mfma_kpad(prec, d), &kappa, &canon);
+    return (kappa + canon) * 1.000001 * 1.000002;
 }
 
 hipError_t launch_mfma_dirs(int prec, bool fold, const double *UT, int64_t d, int64_t m,
                             int64_t ldm, int64_t ncols, int64_t npad, const double *Zb,
                             const double *xbar, void *B0, void *B1, float *cmarg,
-                            const float *amax, double *cq, double *eq, hipStream_t st)
+                            const float *amax, double *cq, double *eq, hipStream_t st,
+                            bool pp)
 {
     double kappa, canon;
     const int64_t kp = mfma_kpad(prec, d);
@@ -949,7 +979,7 @@ hipError_t launch_mfma_dirs(int prec, bool fold, const double *UT, int64_t d, in
     dim3 grid((unsigned)((npad + 63) / 64));
 #define RRS_DIRS(P, F)                                                                        \
     hipLaunchKernelGGL((k_prep_dirs<P, F>), grid, dim3(64), 0, st, UT, d, m, ldm, ncols, npad, \
-                       kp, Zb, xbar, kappa, canon, B0, B1, cmarg, amax, cq, eq)
+                       kp, Zb, xbar, kappa, canon, B0, B1, cmarg, amax, cq, eq, pp ? 1 : 0)
     if (prec == MFMA_BF16) {
         if (fold)
             RRS_DIRS(MFMA_BF16, true);

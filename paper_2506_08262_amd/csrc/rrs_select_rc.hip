@@ -84,6 +84,7 @@ template <int CAP, int STG>
 struct alignas(16) RcShared {
     static constexpr int kCap = CAP, kStage = STG;
     static constexpr bool kShared = false;  // no second histogram / candidate list
+    static constexpr bool kPP = false;      // one error bound for the whole column
     uint32_t hist[kHistN];
     uint32_t skey[64];
     uint32_t srank[64];
@@ -113,6 +114,12 @@ struct alignas(16) RcSharedS : RcShared<CAP, STG> {
     uint32_t ncand2, nlow2;
 };
 
+// Per-point bounds (heavy-tailed data; streamed columns only).
+template <int CAP, int STG>
+struct alignas(16) RcSharedP : RcShared<CAP, STG> {
+    static constexpr bool kPP = true;
+};
+
 // One column and what its exact recomputation needs.
 struct Col {
     const float *s;
@@ -124,6 +131,10 @@ struct Col {
     const double *u;   // [d] direction j, unit stride (LDS copy when d <= kDs)
     int64_t ustride;   // stride of u: 1 for the LDS copy, ldm in global memory
     bool sane;         // binary32 projections finite with room to spare
+    // per-point bounds (heavy-tailed data): |(s_i - c) - t_i| <= alpha |a_i| +
+    // E with an[i] >= |a_i|; null: E alone bounds every point
+    const float *an;
+    double alpha;
 };
 
 // The recipe's projection of point i (EXACT), or the binary32 one shifted.
@@ -508,6 +519,226 @@ __device__ bool rc_range(const SRC &src, float sigf, SH &sh, float &L, float &H)
     return true;
 }
 
+// Ranks r and r + 1 (pair) of the nc candidates of a window: their exact
+// values (phase PH) in sh.cval, then an all-pairs count (up to kQuadG
+// candidates) or a radix select over their keys.  Candidate p's index sits
+// at sh.cidx[p] for p < nc0 and at sh.cidx[kCap - 1 - (p - nc0)] above
+// (two-wave collection layout; nc0 = nc for a single list).
+template <int PH, bool EXACT, class G, class SH>
+__device__ __forceinline__ void rank_window(const Col &C, SH &sh, uint32_t nc, uint32_t nc0,
+                                            uint64_t r, bool pair, double med, double &a,
+                                            double &b)
+{
+    const int tid = G::tid();
+    constexpr uint32_t kCap = (uint32_t)SH::kCap;
+    constexpr uint32_t kQuadG = kQuad < SH::kCap / 2 ? kQuad : SH::kCap / 2;
+    const bool quad = nc <= kQuadG;
+    // index of candidate p in the collection layout
+    auto cand = [&](uint32_t p) -> int64_t {
+        return (int64_t)sh.cidx[p < nc0 ? p : kCap - 1 - (p - nc0)];
+    };
+    const uint32_t dd = (uint32_t)C.d, nd = nc * dd;
+    if (EXACT && nd <= (uint32_t)SH::kStage) {
+        // the candidates' rows in one cooperative round of loads
+        // (coordinate c of candidate p at xs[p d + c]), then each
+        // thread runs its candidate's fma chain from LDS
+        // e / dd = umulhi(e, ceil(2^32 / dd)) for e < 2^16 (d > 1)
+        const uint32_t rcp = 0xFFFFFFFFu / dd + 1u;
+        for (uint32_t e = tid; e < nd; e += G::kN) {
+            const uint32_t p = dd == 1u ? e : __umulhi(e, rcp), c = e - p * dd;
+            sh.xs[e] = C.X[cand(p) * C.d + c];
+        }
+        G::sync();
+        for (uint32_t p = tid; p < nc; p += G::kN)
+            sh.cval[p] = exact_v<PH>(row_t(sh.xs + p * dd, C), med);
+    } else {
+        for (uint32_t p = tid; p < nc; p += G::kN)
+            sh.cval[p] = exact_v<PH>(exact_t<EXACT>(C, cand(p)), med);
+    }
+    G::sync();
+    if (quad) {
+        // the all-pairs ranking counts into cidx[p] (below) and
+        // cidx[kCap / 2 + p] (at most)
+        for (uint32_t p = tid; p < nc; p += G::kN) {
+            sh.cidx[p] = 0u;
+            sh.cidx[kCap / 2 + p] = 0u;
+        }
+        G::sync();
+    }
+    const uint64_t rA = r, rB = r + 1;
+    if (quad) {
+        // candidate p against a slice of the others, G slices
+        // per candidate spread over the block
+        const uint32_t grp = nc >= (uint32_t)G::kN ? 1u : (uint32_t)G::kN / nc;
+        const uint32_t span = (nc + grp - 1) / grp;
+        for (uint32_t w = tid; w < nc * grp; w += G::kN) {
+            const uint32_t g = w / nc, p = w - g * nc;
+            const double mine = sh.cval[p];
+            const uint32_t x0 = g * span, x1 = x0 + span < nc ? x0 + span : nc;
+            uint32_t lt = 0, le = 0;
+            for (uint32_t x = x0; x < x1; ++x) {
+                const double o = sh.cval[x];
+                lt += (o < mine);
+                le += (o <= mine);
+            }
+            if (lt) atomicAdd(&sh.cidx[p], lt);
+            if (le) atomicAdd(&sh.cidx[kCap / 2 + p], le);
+        }
+        G::sync();
+        for (uint32_t p = tid; p < nc; p += G::kN) {
+            const uint32_t lt = sh.cidx[p], le = sh.cidx[kCap / 2 + p];
+            if (lt <= rA && rA < le) sh.resA = sh.cval[p];
+            if (pair && lt <= rB && rB < le) sh.resB = sh.cval[p];
+        }
+        G::sync();
+        a = sh.resA;
+        b = pair ? sh.resB : a;
+    } else {
+        lds_rank_pair<G>(sh, nc, rA, pair);
+        a = sh.resA;
+        b = sh.resB;
+    }
+}
+
+// Points' bound in phase PH: e_i >= |x_i - v_i| with x_i the binary32
+// approximation (s_i in phase 0, |s_i - sig| in phase 1) and v_i its exact
+// counterpart (t_i + c, or |t_i - med|), from the point's own norm bound.
+template <int PH>
+__device__ __forceinline__ double point_bound(const Col &C, float an, float x, double sig)
+{
+    const double Ei = fma(C.alpha, (double)an, C.E);
+    if (PH == 0) return Ei;
+    // the roundings of sig to binary32 and of s - sig
+    return Ei * 1.000001 + 0x1p-22 * (fabs(sig) + fabs((double)x) + Ei) + 1e-300;
+}
+
+// The select with a bound per point (heavy-tailed data, where one bound for
+// the whole column would be the largest point's): point i's exact value lies
+// in [lo_i, hi_i] = [x_i - e_i, x_i + e_i] (binary32, rounded outwards).  One
+// pass bins both ends; with bA the bin of the k-th smallest lower end and bB
+// that of the (k + pair)-th smallest upper end, at most k points lie below
+// L = lin_lo(bA) and at least k + pair + 1 at or below U = lin_hi(bB), so the
+// statistics lie in [L, U].  The window pass counts the points certainly
+// below (hi_i < L) and collects those whose interval meets [L, U]; their
+// exact values are ranked.  Long columns narrow the bracket while the window
+// would hold too many; a miss falls back like the uniform-bound select.
+template <int PH, bool EXACT, class G, class SRC, class SH>
+__device__ __forceinline__ bool rc_select_pp(const Col &C, const SRC &src, double med, double sig, uint64_t k,
+                             bool pair, double &a, double &b, uint64_t *below, SH &sh,
+                             uint32_t *stats)
+{
+    const int tid = G::tid(), lane = tid & 63;
+    constexpr uint32_t kCap = (uint32_t)SH::kCap;
+    static_assert(SH::kCap >= kHistN, "the upper ends' histogram borrows cidx");
+    const float sigf = (float)sig;
+    const float *an = C.an;
+    // interval ends of slot i with approximation sv (binary32, outwards)
+    auto ends = [&](int i, float sv, float &lo, float &hi) {
+        const float x = approx_v<PH>(sv, sigf);
+        const double e = point_bound<PH>(C, an[i], x, sig);
+        lo = __double2float_rd((double)x - e);
+        hi = __double2float_ru((double)x + e);
+    };
+    bool fast = C.sane;
+    float scale = 1.0f, off = 0.0f, L = 0.0f, H = 0.0f;
+    if (fast) fast = rc_range<PH, G>(src, sigf, sh, L, H);
+    if (fast) lin_fit(L, H, scale, off);
+    uint32_t bA = 0, bB = 0;
+    const float lo_l = -(float)(lane + 1), hi_l = (float)(kBins + lane);
+    for (int level = 0; fast; ++level) {
+        for (int x = tid; x < kHistN; x += G::kN) {
+            sh.hist[x] = 0;
+            sh.cidx[x] = 0;
+        }
+        G::sync();
+        src.each([&](int i, float sv) {
+            if (!(sv < __builtin_inff())) return;  // slots past n
+            float lo, hi;
+            ends(i, sv, lo, hi);
+            atomicAdd(&sh.hist[kHistLo + lin_slot(lo, scale, off, lo_l, hi_l)], 1u);
+            atomicAdd(&sh.cidx[kHistLo + lin_slot(hi, scale, off, lo_l, hi_l)], 1u);
+        });
+        G::sync();
+        {
+            uint32_t blo = sh.hist[lane], bhi = sh.cidx[lane];  // the below slots
+            for (int o = 32; o > 0; o >>= 1) {
+                blo += (uint32_t)__shfl_xor((int)blo, o);
+                bhi += (uint32_t)__shfl_xor((int)bhi, o);
+            }
+            uint32_t xA, rA, cA, xB, rB, cB;
+            bool fA, fB;
+            scan_hist(sh.hist + kHistLo, blo, k, xA, rA, cA, fA);
+            scan_hist(sh.cidx + kHistLo, bhi, k + (pair ? 1 : 0), xB, rB, cB, fB);
+            const uint64_t ma = __ballot(fA), mb = __ballot(fB);
+            fast = ma != 0 && mb != 0;
+            if (fast) {
+                bA = (uint32_t)__builtin_amdgcn_readlane((int)xA, __ffsll((long long)ma) - 1);
+                bB = (uint32_t)__builtin_amdgcn_readlane((int)xB, __ffsll((long long)mb) - 1);
+            }
+        }
+        if (!fast || level >= SRC::kMaxLevel) break;
+        // window estimate: the ends falling in bins bA .. bB
+        uint32_t held = 0;
+        for (uint32_t x = bA; x <= bB; ++x) held += sh.hist[kHistLo + x] + sh.cidx[kHistLo + x];
+        if (held <= kCap / 2) break;
+        const float nL = __double2float_rd(lin_lo(bA, scale, off));
+        const float nH = __double2float_ru(lin_hi(bB, scale, off));
+        float ns, no;
+        lin_fit(nL, nH, ns, no);
+        if (!(ns > scale)) break;  // no finer bins to be had
+        scale = ns;
+        off = no;
+        G::sync();
+    }
+    if (fast) {
+        const float Lf = __double2float_rd(lin_lo(bA, scale, off));
+        const float Uf = __double2float_ru(lin_hi(bB, scale, off));
+        G::sync();
+        if (tid == 0) {
+            sh.ncand = 0;
+            sh.count = 0;
+        }
+        G::sync();
+        uint32_t nb = 0;  // this lane's points certainly below
+        src.each([&](int i, float sv) {
+            if (!(sv < __builtin_inff())) return;
+            float lo, hi;
+            ends(i, sv, lo, hi);
+            if (hi < Lf) {
+                ++nb;
+            } else if (lo <= Uf) {
+                const uint32_t p = atomicAdd(&sh.ncand, 1u);
+                if (p < kCap) sh.cidx[p] = (uint32_t)i;
+            }
+        });
+        for (int o = 32; o > 0; o >>= 1) nb += (uint32_t)__shfl_xor((int)nb, o);
+        if (lane == 0 && nb) atomicAdd(&sh.count, nb);
+        G::sync();
+        const uint32_t nc = sh.ncand;
+        const uint64_t B = sh.count;
+        G::sync();
+        fast = nc <= kCap && B <= k && k + (pair ? 1 : 0) < B + nc;
+        if (fast) {
+            rank_window<PH, EXACT, G>(C, sh, nc, nc, k - B, pair, med, a, b);
+            *below = B;
+            return true;
+        }
+    }
+    G::sync();
+    if (SRC::kMaxLevel == 0 && C.sane) {
+        // a register-resident column that missed: the streamed select over
+        // the same column in global memory
+        return rc_select_pp<PH, EXACT, G>(C, StreamSrc<G>{C.s, C.n}, med, sig, k, pair, a, b,
+                                          below, sh, stats);
+    }
+    if (stats && tid == 0) stat_fallback(stats);
+    const uint64_t A = rc_radix_kth<PH, EXACT, G>(C, med, k, sh);
+    a = key_value(A);
+    b = a;
+    if (pair) b = key_value(rc_radix_next<PH, EXACT, G>(C, med, k, A, sh));
+    return false;
+}
+
 // The exact values of ranks k (and k + 1 if pair) in phase PH.  Returns true
 // when the window path served them; then sh.cval[0 .. ncand) holds the
 // window's exact values and *below the number of points under the window.
@@ -518,9 +749,10 @@ __device__ __forceinline__ bool rc_select(const Col &C, const SRC &src, double m
 {
     const int tid = G::tid(), lane = tid & 63, wave = tid >> 6;
     constexpr uint32_t kCap = (uint32_t)SH::kCap;
-    constexpr uint32_t kQuadG = kQuad < SH::kCap / 2 ? kQuad : SH::kCap / 2;
     const int64_t n = C.n;
     const float sigf = (float)sig;
+    if constexpr (SH::kPP)
+        return rc_select_pp<PH, EXACT, G>(C, src, med, sig, k, pair, a, b, below, sh, stats);
     bool fast = C.sane;
     float scale = 1.0f, off = 0.0f;
     int fast0 = 0;
@@ -714,72 +946,7 @@ __device__ __forceinline__ bool rc_select(const Col &C, const SRC &src, double m
             const uint64_t B = (uint64_t)beforeA - nlow;
             fast = nc <= kCap && B <= k && k + (pair ? 1 : 0) < B + nc;
             if (fast) {
-                const bool quad = nc <= kQuadG;
-                // index of candidate p in the collection layout
-                auto cand = [&](uint32_t p) -> int64_t {
-                    return (int64_t)sh.cidx[p < nc0 ? p : kCap - 1 - (p - nc0)];
-                };
-                const uint32_t dd = (uint32_t)C.d, nd = nc * dd;
-                if (EXACT && nd <= (uint32_t)SH::kStage) {
-                    // the candidates' rows in one cooperative round of loads
-                    // (coordinate c of candidate p at xs[p d + c]), then each
-                    // thread runs its candidate's fma chain from LDS
-                    // e / dd = umulhi(e, ceil(2^32 / dd)) for e < 2^16 (d > 1)
-                    const uint32_t rcp = 0xFFFFFFFFu / dd + 1u;
-                    for (uint32_t e = tid; e < nd; e += G::kN) {
-                        const uint32_t p = dd == 1u ? e : __umulhi(e, rcp), c = e - p * dd;
-                        sh.xs[e] = C.X[cand(p) * C.d + c];
-                    }
-                    G::sync();
-                    for (uint32_t p = tid; p < nc; p += G::kN)
-                        sh.cval[p] = exact_v<PH>(row_t(sh.xs + p * dd, C), med);
-                } else {
-                    for (uint32_t p = tid; p < nc; p += G::kN)
-                        sh.cval[p] = exact_v<PH>(exact_t<EXACT>(C, cand(p)), med);
-                }
-                G::sync();
-                if (quad) {
-                    // the all-pairs ranking counts into cidx[p] (below) and
-                    // cidx[kCap / 2 + p] (at most)
-                    for (uint32_t p = tid; p < nc; p += G::kN) {
-                        sh.cidx[p] = 0u;
-                        sh.cidx[kCap / 2 + p] = 0u;
-                    }
-                    G::sync();
-                }
-                const uint64_t rA = k - B, rB = k + 1 - B;
-                if (quad) {
-                    // candidate p against a slice of the others, G slices
-                    // per candidate spread over the block
-                    const uint32_t grp = nc >= (uint32_t)G::kN ? 1u : (uint32_t)G::kN / nc;
-                    const uint32_t span = (nc + grp - 1) / grp;
-                    for (uint32_t w = tid; w < nc * grp; w += G::kN) {
-                        const uint32_t g = w / nc, p = w - g * nc;
-                        const double mine = sh.cval[p];
-                        const uint32_t x0 = g * span, x1 = x0 + span < nc ? x0 + span : nc;
-                        uint32_t lt = 0, le = 0;
-                        for (uint32_t x = x0; x < x1; ++x) {
-                            const double o = sh.cval[x];
-                            lt += (o < mine);
-                            le += (o <= mine);
-                        }
-                        if (lt) atomicAdd(&sh.cidx[p], lt);
-                        if (le) atomicAdd(&sh.cidx[kCap / 2 + p], le);
-                    }
-                    G::sync();
-                    for (uint32_t p = tid; p < nc; p += G::kN) {
-                        const uint32_t lt = sh.cidx[p], le = sh.cidx[kCap / 2 + p];
-                        if (lt <= rA && rA < le) sh.resA = sh.cval[p];
-                        if (pair && lt <= rB && rB < le) sh.resB = sh.cval[p];
-                    }
-                    G::sync();
-                    a = sh.resA;
-                    b = pair ? sh.resB : a;
-                } else {
-                    lds_rank_pair<G>(sh, nc, rA, pair);
-                    a = sh.resA;
-                    b = sh.resB;
-                }
+                rank_window<PH, EXACT, G>(C, sh, nc, nc0, k - B, pair, med, a, b);
                 *below = B;
                 return true;
             }
@@ -981,7 +1148,8 @@ __device__ __forceinline__ int rc_apd_shared(const Col &C, const StreamSrc<G> &s
     const int tid = G::tid();
     constexpr uint32_t kCap = (uint32_t)SH::kCap;
     const int64_t n = C.n;
-    if (!C.sane) return 0;
+    // per-point bounds (heavy tails) take the separate selects
+    if (!C.sane || C.an) return 0;
     const bool odd = (n & 1) != 0;
     const uint64_t k = odd ? (uint64_t)n / 2 : (uint64_t)n / 2 - 1;
     // MAD_+'s rank when no other point equals the median
@@ -1142,7 +1310,7 @@ __device__ __forceinline__ double rc_depth(const Col &C, const SRC &src, SH &sh,
 // One column per group G (a workgroup of two or four waves, or a 64-thread
 // workgroup of one wave).  VPT > 0: the column in registers (n <= G::kN VPT); VPT == 0:
 // streamed.
-template <int NOTION, bool EXACT, int VPT, class G, class SH>
+template <int NOTION, bool EXACT, int VPT, class G, class SH, bool PP>
 __device__ __forceinline__ void select_column(const float *__restrict__ S, int64_t n, int64_t m,
                                               int64_t ldm, const double *__restrict__ cq,
                                               const double *__restrict__ eq,
@@ -1150,6 +1318,7 @@ __device__ __forceinline__ void select_column(const float *__restrict__ S, int64
                                               const double *__restrict__ Zb,
                                               const double *__restrict__ UT,
                                               double *__restrict__ Dj, uint32_t *__restrict__ stats,
+                                              const float *__restrict__ anorm, double alpha,
                                               SH &sh)
 {
     const int tid = G::tid();
@@ -1165,6 +1334,9 @@ __device__ __forceinline__ void select_column(const float *__restrict__ S, int64
         C.sane = e < 0x1p100;
         C.E = EXACT ? e : 0.0;
     }
+    // heavy-tailed data: a bound per point (E is then the column part)
+    C.an = (EXACT && PP) ? anorm : nullptr;
+    C.alpha = alpha;
     C.X = X;
     C.d = d;
     if (EXACT && d <= kDs) {
@@ -1199,7 +1371,7 @@ __device__ __forceinline__ void select_column(const float *__restrict__ S, int64
     if (tid == 0) Dj[qi * ldm + j] = D;
 }
 
-template <int NOTION, bool EXACT, int VPT, class G, int CAP, int STG>
+template <int NOTION, bool EXACT, int VPT, class G, int CAP, int STG, bool PP>
 __global__ __launch_bounds__(G::kN) void k_select_rc(const float *__restrict__ S, int64_t n,
                                                      int64_t m, int64_t ldm,
                                                      const double *__restrict__ cq,
@@ -1208,21 +1380,28 @@ __global__ __launch_bounds__(G::kN) void k_select_rc(const float *__restrict__ S
                                                      const double *__restrict__ Zb,
                                                      const double *__restrict__ UT,
                                                      double *__restrict__ Dj,
-                                                     uint32_t *__restrict__ stats)
+                                                     uint32_t *__restrict__ stats,
+                                                     const float *__restrict__ anorm,
+                                                     double alpha)
 {
-    // streamed APD columns (VPT == 0) carry the second histogram and list
-    using SH = typename std::conditional<VPT == 0 && NOTION == NOTION_APD, RcSharedS<CAP, STG>,
-                                         RcShared<CAP, STG>>::type;
+    // streamed APD columns (VPT == 0) carry the second histogram and list;
+    // per-point bounds mark their type
+    using SH = typename std::conditional<
+        PP, RcSharedP<CAP, STG>,
+        typename std::conditional<VPT == 0 && NOTION == NOTION_APD, RcSharedS<CAP, STG>,
+                                  RcShared<CAP, STG>>::type>::type;
     __shared__ SH sh;
-    select_column<NOTION, EXACT, VPT, G, SH>(S, n, m, ldm, cq, eq, X, d, Zb, UT, Dj, stats, sh);
+    select_column<NOTION, EXACT, VPT, G, SH, PP>(S, n, m, ldm, cq, eq, X, d, Zb, UT, Dj, stats,
+                                                 anorm, alpha, sh);
 }
 
-template <int NOTION, bool EXACT, int VPT, class G, int CAP, int STG>
+template <int NOTION, bool EXACT, int VPT, class G, int CAP, int STG, bool PP = false>
 hipError_t launch_rc(const SelectRcArgs &a, hipStream_t st)
 {
     dim3 grid((unsigned)a.m, (unsigned)a.qb);
-    hipLaunchKernelGGL((k_select_rc<NOTION, EXACT, VPT, G, CAP, STG>), grid, dim3(G::kN), 0, st, a.S,
-                       a.n, a.m, a.ldm, a.cq, a.eq, a.X, a.d, a.Z, a.UT, a.Dj, a.stats);
+    hipLaunchKernelGGL((k_select_rc<NOTION, EXACT, VPT, G, CAP, STG, PP>), grid, dim3(G::kN), 0, st,
+                       a.S, a.n, a.m, a.ldm, a.cq, a.eq, a.X, a.d, a.Z, a.UT, a.Dj, a.stats,
+                       a.anorm, a.alpha);
     return hipGetLastError();
 }
 
@@ -1233,6 +1412,9 @@ hipError_t launch_rc(const SelectRcArgs &a, hipStream_t st)
 template <int NOTION, bool EXACT>
 hipError_t launch_rc_vpt(const SelectRcArgs &a, hipStream_t st)
 {
+    // per-point bounds (heavy-tailed data): the streamed kernel, any n
+    if constexpr (EXACT)
+        if (a.pp) return launch_rc<NOTION, EXACT, 0, BlockG<4>, kCapW, 64, true>(a, st);
     const int64_t w = (a.n + 63) / 64;
     if (w <= 8) return launch_rc<NOTION, EXACT, 8, WaveG, kCapWave, 512>(a, st);
     if (w <= 16) return launch_rc<NOTION, EXACT, 16, WaveG, kCapWave, 512>(a, st);

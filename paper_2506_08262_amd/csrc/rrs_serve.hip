@@ -117,6 +117,7 @@ struct rrs_dataset {
         void *A0 = nullptr, *A1 = nullptr;
         float *anorm = nullptr;
         float *amax = nullptr;
+        bool pp = false;
         hipEvent_t ready = nullptr;
     } ops[3];
     int refs = 0;               // requests submitted and not finished
@@ -245,6 +246,13 @@ rrs_status launch_request(rrs_ctx *c, rrs_request *r, int slot, bool prep_ops)
             o.amax = oc.take<float>(16);
             RRS_HIP_TRY(rrs::launch_mfma_prep(prec, ds->base.X, ds->n, d, o.xbar, o.A0, o.A1,
                                               o.anorm, o.amax, st));
+            // per-point bounds for heavy-tailed data (a one-time wait for
+            // this data set's preparation)
+            rrs::DataDev t;
+            t.prec = prec;
+            t.amax = o.amax;
+            RRS_HIP_TRY(rrs::data_point_bounds(t, st));
+            o.pp = t.pp;
             RRS_HIP_TRY(hipEventCreateWithFlags(&o.ready, hipEventDisableTiming));
             RRS_HIP_TRY(hipEventRecord(o.ready, st));
         } else {
@@ -256,6 +264,7 @@ rrs_status launch_request(rrs_ctx *c, rrs_request *r, int slot, bool prep_ops)
         D.A1 = o.A1;
         D.anorm = o.anorm;
         D.amax = o.amax;
+        D.pp = o.pp;
     }
     rrs::JobIO io;
     io.Z = Zd;

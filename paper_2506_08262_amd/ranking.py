@@ -61,10 +61,11 @@ def rank_correlations(a: np.ndarray, b: np.ndarray) -> dict:
 
 def study(d: int, n: int = 100_000, queries: int = 5000, K: int = 100_000, n_refine: int = 40,
           cap_shrink: float = 0.9, law: str = "gaussian", nu: float = 0.0, seed: int = 0,
-          precision: str = "f32", device: str = "cuda:0") -> dict:
-    """One column of the study: depths D_P and D_AP (GPU) and D_M(L) (host) of
-    `queries` points drawn from the n-point data set, correlated with the
-    true density and with each other."""
+          precision: str = "f32", device: str = "cuda:0", first_cap: bool = False) -> dict:
+    """One column of the study: depths D_P and D_AP and D_M(L) (all on the
+    GPU) of `queries` points drawn from the n-point data set, correlated with
+    the true density and with each other.  first_cap: refinement 1 draws in
+    the half-angle pi/2 cap around e1 (Alg. S4) instead of on the sphere."""
     import torch
 
     from . import rrs
@@ -76,12 +77,14 @@ def study(d: int, n: int = 100_000, queries: int = 5000, K: int = 100_000, n_ref
     Xt = torch.from_numpy(X).to(device)
     Zt = torch.from_numpy(Z).to(device)
     out = {"d": d, "n": n, "queries": queries, "K": K, "n_refine": n_refine,
-           "cap_shrink": cap_shrink, "law": law, "nu": nu, "precision": precision}
+           "cap_shrink": cap_shrink, "law": law, "nu": nu, "precision": precision,
+           "first_cap": first_cap}
     depths = {}
     for notion in ("projection", "apd"):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        res = rrs.depth(notion, Xt, Zt, K, n_refine, cap_shrink, seed, precision=precision)
+        res = rrs.depth(notion, Xt, Zt, K, n_refine, cap_shrink, seed, precision=precision,
+                        first_cap=first_cap)
         torch.cuda.synchronize()
         sec = time.perf_counter() - t0
         depths[notion] = res["depth"].cpu().numpy()
@@ -109,15 +112,17 @@ def main(argv=None) -> None:
     ap.add_argument("--n-refine", type=int, default=40)
     ap.add_argument("--cap-shrink", type=float, default=0.9)
     ap.add_argument("--precision", default="f32")
-    ap.add_argument("--t-precision", default="f64",
-                    help="precision form for the Student t laws: their heavy tails make the "
-                         "error bound of the matrix-core forms (which grows with the largest "
-                         "data norm) cover whole columns")
+    ap.add_argument("--t-precision", default="f32",
+                    help="precision form for the Student t laws (their heavy tails switch the "
+                         "matrix-core forms' selects to per-point error bounds)")
+    ap.add_argument("--first-cap", action="store_true",
+                    help="refinement 1 in the pi/2 cap around e1 instead of on the sphere")
     args = ap.parse_args(argv)
     runs = [("gaussian", 0.0, d) for d in args.dims] + [("t", nu, 50) for nu in args.nus]
     for law, nu, d in runs:
         r = study(d, args.n, args.queries, args.K, args.n_refine, args.cap_shrink, law, nu,
-                  precision=args.precision if law == "gaussian" else args.t_precision)
+                  precision=args.precision if law == "gaussian" else args.t_precision,
+                  first_cap=args.first_cap)
         print(json.dumps(r), flush=True)
         print(f"[ranking] {law} nu={nu} d={d} done", file=sys.stderr, flush=True)
 

@@ -217,6 +217,10 @@ def small(notion: str, n: int, d: int, nq: int, K: int, n_refine: int, cap_shrin
     elif law == "integer":
         X = rng.integers(-50, 51, (n, d)).astype(np.float64)
         Z = rng.integers(-20, 21, (nq, d)).astype(np.float64)
+    elif law.startswith("t") and law[1:].isdigit():
+        # multivariate Student t with nu = int(law[1:]) degrees of freedom
+        X = student_t(rng, n, d, float(law[1:]))
+        Z = student_t(rng, nq, d, float(law[1:]))
     else:
         raise ValueError(law)
     return Workload(f"small-{law}", notion, np.ascontiguousarray(X), np.ascontiguousarray(Z),
