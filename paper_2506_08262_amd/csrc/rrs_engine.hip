@@ -9,6 +9,8 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstdlib>
+#include <cstring>
+#include <math.h>
 
 namespace rrs {
 
@@ -182,8 +184,22 @@ hipError_t data_point_bounds(DataDev &D, hipStream_t st)
     uint32_t w[4] = {0u, 0u, 0u, 0u};
     hipError_t e = hipMemcpyAsync(w, D.amax, sizeof(w), hipMemcpyDeviceToHost, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
-    if (e == hipSuccess) D.pp = w[1] != 0u;
-    return e;
+    if (e != hipSuccess) return e;
+    // candidates a column-wide bound E = alpha max|a| would put in a window
+    // around the median: about 4 E times the points per unit near it,
+    // n / (2.5 rms / sqrt(d)) for a projection of spread rms / sqrt(d);
+    // per-point bounds once that passes a quarter of the candidate room
+    float amax;
+    double sum;
+    std::memcpy(&amax, &w[0], sizeof(amax));
+    std::memcpy(&sum, &w[2], sizeof(sum));
+    const double rms = sqrt(sum / (double)(D.n > 0 ? D.n : 1));
+    if (rms > 0.0) {
+        const double est = 4.0 * mfma_point_alpha(D.prec, D.d) * (double)amax * (double)D.n *
+                           sqrt((double)D.d) / (2.5 * rms);
+        D.pp = est > 256.0;
+    }
+    return hipSuccess;
 }
 
 int job_mfma_prec(int precision)

@@ -102,8 +102,10 @@ size_t data_bytes(int64_t n, int64_t d, int prec);
 // Carves the prepared arrays from mem (data_bytes(n, d, prec) bytes) and
 // enqueues their preparation from D.X on st.
 hipError_t data_prepare(DataDev &D, void *mem, int prec, hipStream_t st);
-// Whether the stored-projection selects take per-point bounds on this data
-// (waits for the preparation; RRS_POINT_BOUNDS = 0 / 1 forces it off / on).
+// Whether the stored-projection selects take per-point bounds on this data:
+// when the column-wide bound, set by the largest norm, would fill a window
+// with too many candidates (waits for the preparation; RRS_POINT_BOUNDS =
+// 0 / 1 forces it off / on).
 hipError_t data_point_bounds(DataDev &D, hipStream_t st);
 
 // ---------------------------------------------------------------------------

@@ -113,9 +113,8 @@ int64_t mfma_kpad(int prec, int64_t d);
 size_t mfma_elem_bytes(int prec);
 int mfma_terms(int prec);
 void mfma_margins(int prec, int64_t d, int64_t kp, double *kappa, double *canon);
-// amax: 16 words; [0] the largest norm bound, [1] the per-point-bound flag
-// (set when that norm exceeds 4x the root mean square norm), [2..3] the sum
-// of squared norms (binary64).
+// amax: 16 words; [0] the largest norm bound, [2..3] the sum of squared
+// norms (binary64).
 hipError_t launch_mfma_prep(int prec, const double *X, int64_t n, int64_t d, double *xbar,
                             void *A0, void *A1, float *anorm, float *amax, hipStream_t st);
 // Per-point factor of the stored-projection bound: point i's bound is

@@ -104,14 +104,6 @@ __global__ __launch_bounds__(256) void k_prep_data(const double *__restrict__ X,
     if ((threadIdx.x & 63) == 0 && w != 0.0) atomicAdd((double *)(amax + 2), w);
 }
 
-// Per-point bounds for heavy-tailed data: the flag is set when the largest
-// norm exceeds 4x the root mean square norm (Gaussian-like data stays below).
-__global__ void k_point_flag(float *__restrict__ amax, int64_t n)
-{
-    const double rms = sqrt(*(const double *)(amax + 2) / (double)n);
-    ((uint32_t *)amax)[1] = (double)amax[0] > 4.0 * rms ? 1u : 0u;
-}
-
 // Per refinement: the directions (binary64, [q][d][ldm] in UT) in the GEMM's
 // operand format, one operand row per flat column J = q m + j (rows ncols ..
 // npad - 1 are zero).  FOLD (sign counts): the centring term is folded in and
@@ -954,9 +946,6 @@ hipError_t launch_mfma_prep(int prec, const double *X, int64_t n, int64_t d, dou
     else
         hipLaunchKernelGGL(k_prep_data<MFMA_F32>, grid, dim3(256), 0, st, X, n, d, kp, xbar, A0,
                            A1, anorm, amax);
-    e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_point_flag, dim3(1), dim3(1), 0, st, amax, n);
     return hipGetLastError();
 }
 

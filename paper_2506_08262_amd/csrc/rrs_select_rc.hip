@@ -519,6 +519,58 @@ __device__ bool rc_range(const SRC &src, float sigf, SH &sh, float &L, float &H)
     return true;
 }
 
+// Bracket from 64 sampled approximations (slot kPer w + l from lane l < kPer
+// of wave w), ranked in LDS: the samples around rank k (and k + 1), 2.5
+// binomial standard deviations plus `widen` sample positions either side;
+// false when fewer than 16 samples are finite.  sh.srank must be zero.
+template <int PH, class G, class SRC, class SH>
+__device__ __forceinline__ bool sampled_bracket(const SRC &src, float sigf, int64_t n, uint64_t k,
+                                                bool pair, double widen, SH &sh, float &scale,
+                                                float &off)
+{
+    const int tid = G::tid(), lane = tid & 63, wave = tid >> 6;
+    constexpr int kPer = 64 / G::kWaves;
+    if (lane < kPer) {
+        const int slot = wave * kPer + lane;
+        const float x = approx_v<PH>(src.sample(slot), sigf);
+        const uint32_t kx = fkey32<PH>(x);
+        sh.skey[slot] = fkey_finite<PH>(kx) ? kx : 0xFFFFFFFFu;
+        sh.sval[slot] = x;
+    }
+    G::sync();
+    {
+        const uint32_t mine = sh.skey[lane];
+        uint32_t part = 0;
+#pragma unroll
+        for (int jj = 0; jj < kPer; ++jj) {
+            const int o = wave * kPer + jj;
+            const uint32_t ko = sh.skey[o];
+            part += (ko < mine || (ko == mine && o < lane)) ? 1u : 0u;
+        }
+        atomicAdd(&sh.srank[lane], part);
+    }
+    G::sync();
+    // every wave derives the bracket itself (same values, no barrier)
+    const uint32_t kx = sh.skey[lane];
+    const bool ok = kx != 0xFFFFFFFFu;
+    const uint32_t rank = sh.srank[lane];
+    const uint32_t S = (uint32_t)__popcll(__ballot(ok));
+    if (S < 16) return false;
+    const double f = ((double)k + 0.5) / (double)n;
+    const double pos = f * (double)S;
+    const double del = 2.5 * sqrt((double)S * f * (1.0 - f)) + 1.5 + widen;
+    double lo = floor(pos - del), hi = ceil(pos + del + (pair ? 1.0 : 0.0));
+    if (lo < 0.0) lo = 0.0;
+    if (hi > (double)(S - 1)) hi = (double)(S - 1);
+    const uint32_t rlo = (uint32_t)lo, rhi = (uint32_t)hi;
+    const uint64_t mlo = __ballot(ok && rank == rlo), mhi = __ballot(ok && rank == rhi);
+    const float xv = sh.sval[lane];
+    const float L = lane_bcast_f(xv, __ffsll((long long)mlo) - 1);
+    const float H = lane_bcast_f(xv, __ffsll((long long)mhi) - 1);
+    lin_fit(L, H, scale, off);
+    return true;
+}
+
 // Ranks r and r + 1 (pair) of the nc candidates of a window: their exact
 // values (phase PH) in sh.cval, then an all-pairs count (up to kQuadG
 // candidates) or a radix select over their keys.  Candidate p's index sits
@@ -600,16 +652,20 @@ __device__ __forceinline__ void rank_window(const Col &C, SH &sh, uint32_t nc, u
     }
 }
 
-// Points' bound in phase PH: e_i >= |x_i - v_i| with x_i the binary32
-// approximation (s_i in phase 0, |s_i - sig| in phase 1) and v_i its exact
-// counterpart (t_i + c, or |t_i - med|), from the point's own norm bound.
+// Interval [lo, hi] around approximation x (binary32) holding its exact
+// counterpart (t_i + c, or |t_i - med| in phase 1), from the point's own
+// norm bound an: e = alpha an + E (alpha_f, E_f rounded up), widened by the
+// fma's rounding, in phase 1 by the roundings of sig and of s - sig, and by
+// the roundings of x -/+ e themselves, all in binary32.
 template <int PH>
-__device__ __forceinline__ double point_bound(const Col &C, float an, float x, double sig)
+__device__ __forceinline__ void point_ends(float x, float an, float alpha_f, float E_f,
+                                           float sigf, float &lo, float &hi)
 {
-    const double Ei = fma(C.alpha, (double)an, C.E);
-    if (PH == 0) return Ei;
-    // the roundings of sig to binary32 and of s - sig
-    return Ei * 1.000001 + 0x1p-22 * (fabs(sig) + fabs((double)x) + Ei) + 1e-300;
+    float e = fmaf(alpha_f, an, E_f) * (1.0f + 0x1p-22f);
+    if (PH == 1) e = fmaf(0x1p-21f, fabsf(sigf) + fabsf(x) + e, e) * (1.0f + 0x1p-22f);
+    e = fmaf(0x1p-22f, fabsf(x) + e, e) + 0x1p-149f;
+    lo = x - e;
+    hi = x + e;
 }
 
 // The select with a bound per point (heavy-tailed data, where one bound for
@@ -632,17 +688,26 @@ __device__ __forceinline__ bool rc_select_pp(const Col &C, const SRC &src, doubl
     static_assert(SH::kCap >= kHistN, "the upper ends' histogram borrows cidx");
     const float sigf = (float)sig;
     const float *an = C.an;
+    const float alpha_f = __double2float_ru(C.alpha), E_f = __double2float_ru(C.E);
     // interval ends of slot i with approximation sv (binary32, outwards)
     auto ends = [&](int i, float sv, float &lo, float &hi) {
-        const float x = approx_v<PH>(sv, sigf);
-        const double e = point_bound<PH>(C, an[i], x, sig);
-        lo = __double2float_rd((double)x - e);
-        hi = __double2float_ru((double)x + e);
+        point_ends<PH>(approx_v<PH>(sv, sigf), an[i], alpha_f, E_f, sigf, lo, hi);
     };
     bool fast = C.sane;
-    float scale = 1.0f, off = 0.0f, L = 0.0f, H = 0.0f;
-    if (fast) fast = rc_range<PH, G>(src, sigf, sh, L, H);
-    if (fast) lin_fit(L, H, scale, off);
+    float scale = 1.0f, off = 0.0f;
+    bool whole = false;  // bracket over the column's whole range
+    if (fast) {
+        if (tid < 64) sh.srank[tid] = 0;
+        G::sync();
+        // the sampled centres' bracket, widened by two sample positions for
+        // the interval ends; the column's range when too few are finite
+        if (!sampled_bracket<PH, G>(src, sigf, C.n, k, pair, 2.0, sh, scale, off)) {
+            float L, H;
+            fast = rc_range<PH, G>(src, sigf, sh, L, H);
+            if (fast) lin_fit(L, H, scale, off);
+            whole = true;
+        }
+    }
     uint32_t bA = 0, bB = 0;
     const float lo_l = -(float)(lane + 1), hi_l = (float)(kBins + lane);
     for (int level = 0; fast; ++level) {
@@ -676,7 +741,19 @@ __device__ __forceinline__ bool rc_select_pp(const Col &C, const SRC &src, doubl
                 bB = (uint32_t)__builtin_amdgcn_readlane((int)xB, __ffsll((long long)mb) - 1);
             }
         }
-        if (!fast || level >= SRC::kMaxLevel) break;
+        if (level >= SRC::kMaxLevel) break;
+        if (!fast) {
+            // the sampled bracket missed a rank: bracket the whole column
+            // instead (then narrow as usual)
+            if (whole) break;
+            float L, H;
+            fast = rc_range<PH, G>(src, sigf, sh, L, H);
+            if (!fast) break;
+            lin_fit(L, H, scale, off);
+            whole = true;
+            G::sync();
+            continue;
+        }
         // window estimate: the ends falling in bins bA .. bB
         uint32_t held = 0;
         for (uint32_t x = bA; x <= bB; ++x) held += sh.hist[kHistLo + x] + sh.cidx[kHistLo + x];
@@ -763,50 +840,7 @@ __device__ __forceinline__ bool rc_select(const Col &C, const SRC &src, double m
             sh.ncand = 0;
             sh.nlow = 0;
         }
-        // 64 sampled approximations: slot kPer w + l from lane l < kPer of wave w
-        constexpr int kPer = 64 / G::kWaves;
-        if (lane < kPer) {
-            const int slot = wave * kPer + lane;
-            const float x = approx_v<PH>(src.sample(slot), sigf);
-            const uint32_t kx = fkey32<PH>(x);
-            sh.skey[slot] = fkey_finite<PH>(kx) ? kx : 0xFFFFFFFFu;
-            sh.sval[slot] = x;
-        }
-        G::sync();
-        {
-            const uint32_t mine = sh.skey[lane];
-            uint32_t part = 0;
-#pragma unroll
-            for (int jj = 0; jj < kPer; ++jj) {
-                const int o = wave * kPer + jj;
-                const uint32_t ko = sh.skey[o];
-                part += (ko < mine || (ko == mine && o < lane)) ? 1u : 0u;
-            }
-            atomicAdd(&sh.srank[lane], part);
-        }
-        G::sync();
-        {
-            // every wave derives the bracket itself (same values, no barrier)
-            const uint32_t kx = sh.skey[lane];
-            const bool ok = kx != 0xFFFFFFFFu;
-            const uint32_t rank = sh.srank[lane];
-            const uint32_t S = (uint32_t)__popcll(__ballot(ok));
-            fast0 = S >= 16 ? 1 : 0;
-            if (fast0) {
-                const double f = ((double)k + 0.5) / (double)n;
-                const double pos = f * (double)S;
-                const double del = 2.5 * sqrt((double)S * f * (1.0 - f)) + 1.5;
-                double lo = floor(pos - del), hi = ceil(pos + del + (pair ? 1.0 : 0.0));
-                if (lo < 0.0) lo = 0.0;
-                if (hi > (double)(S - 1)) hi = (double)(S - 1);
-                const uint32_t rlo = (uint32_t)lo, rhi = (uint32_t)hi;
-                const uint64_t mlo = __ballot(ok && rank == rlo), mhi = __ballot(ok && rank == rhi);
-                const float xv = sh.sval[lane];
-                const float L = lane_bcast_f(xv, __ffsll((long long)mlo) - 1);
-                const float H = lane_bcast_f(xv, __ffsll((long long)mhi) - 1);
-                lin_fit(L, H, scale, off);
-            }
-        }
+        fast0 = sampled_bracket<PH, G>(src, sigf, n, k, pair, 0.0, sh, scale, off) ? 1 : 0;
         // register-resident columns keep a single pass (a miss falls back);
         // streamed columns rebracket and narrow instead
         fast = SRC::kMaxLevel > 0 || fast0 != 0;
