@@ -111,23 +111,30 @@ __global__ __launch_bounds__(256) void k_prep_data(const double *__restrict__ X,
 // projections): the centring columns are zero, cq[J] = c_j and eq[J] bounds
 // |(s_ij - c_j) - t_ij| for every point i, with t_ij the recipe's binary64
 // projection: kappa max|a| + canon (max|a| + 2 |z - xbar|).
+//
+// Four lanes per column: lane t of the quad converts the 16-byte pieces
+// g = t, t + 4, ... of the row (8 bf16 or 4 binary32 elements), so that a
+// quad writes 64 contiguous bytes per step and a wave keeps 16 columns' loads
+// in flight.  c_j = (z - xbar).u and |z - xbar|^2 are summed per lane and
+// then over the quad; the pieces from coordinate d on (centring columns and
+// padding) are written after that sum.  The order of the sum only moves c_j
+// by rounding, which the canon term of the margin covers for any order.
 template <int PREC, bool FOLD>
-__global__ __launch_bounds__(64) void k_prep_dirs(const double *__restrict__ UT, int64_t d,
-                                                  int64_t m, int64_t ldm, int64_t ncols,
-                                                  int64_t npad, int64_t kp,
-                                                  const double *__restrict__ Zb,
-                                                  const double *__restrict__ xbar, double kappa,
-                                                  double canon, void *__restrict__ B0,
-                                                  void *__restrict__ B1,
-                                                  float *__restrict__ cmarg,
-                                                  const float *__restrict__ amax,
-                                                  double *__restrict__ cq,
-                                                  double *__restrict__ eq, int pp)
+__global__ __launch_bounds__(256) void k_prep_dirs(const double *__restrict__ UT, int64_t d,
+                                                   int64_t m, int64_t ldm, int64_t ncols,
+                                                   int64_t npad, int64_t kp,
+                                                   const double *__restrict__ Zb,
+                                                   const double *__restrict__ xbar, double kappa,
+                                                   double canon, void *__restrict__ B0,
+                                                   void *__restrict__ B1,
+                                                   float *__restrict__ cmarg,
+                                                   const float *__restrict__ amax,
+                                                   double *__restrict__ cq,
+                                                   double *__restrict__ eq, int pp)
 {
-    const int64_t J = (int64_t)blockIdx.x * 64 + threadIdx.x;
-    if (J >= npad) return;
-    // a thread writes its operand row in 16-byte pieces (8 bf16 or 4 binary32
-    // elements; kp is a multiple of 16 or 8, rows start 16-byte aligned)
+    const int t = threadIdx.x & 3;
+    const int64_t J = (int64_t)blockIdx.x * 64 + (threadIdx.x >> 2);
+    if (J >= npad) return;  // uniform within a quad
     constexpr int kE = PREC == MFMA_BF16 ? 8 : 4;
     typedef __attribute__((ext_vector_type(8))) __bf16 v8bf;
     typedef __attribute__((ext_vector_type(4))) float v4f;
@@ -136,7 +143,7 @@ __global__ __launch_bounds__(64) void k_prep_dirs(const double *__restrict__ UT,
     v8bf *l8 = (v8bf *)B1 + J * pieces;
     v4f *f4 = (v4f *)B0 + J * pieces;
     if (J >= ncols) {
-        for (int64_t g = 0; g < pieces; ++g) {
+        for (int64_t g = t; g < pieces; g += 4) {
             if (PREC == MFMA_BF16) {
                 h8[g] = v8bf{};
                 l8[g] = v8bf{};
@@ -144,19 +151,22 @@ __global__ __launch_bounds__(64) void k_prep_dirs(const double *__restrict__ UT,
                 f4[g] = v4f{};
             }
         }
-        if (FOLD) {
-            cmarg[J] = 0.0f;
-        } else {
-            cq[J] = 0.0;
-            eq[J] = 0.0;
+        if (t == 0) {
+            if (FOLD) {
+                cmarg[J] = 0.0f;
+            } else {
+                cq[J] = 0.0;
+                eq[J] = 0.0;
+            }
         }
         return;
     }
     const int64_t qi = J / m, j = J - qi * m;
     const double *u = UT + qi * d * ldm + j;
     const double *z = Zb + qi * d;
+    const int64_t gfull = d / kE;  // pieces made of coordinates c < d only
     double cj = 0.0, bn = 0.0;
-    for (int64_t g = 0; g < pieces; ++g) {
+    for (int64_t g = t; g < pieces; g += 4) {
         v8bf vh{}, vl{};
         v4f vf{};
 #pragma unroll
@@ -167,6 +177,37 @@ __global__ __launch_bounds__(64) void k_prep_dirs(const double *__restrict__ UT,
                 const double b = z[c] - xbar[c];
                 cj = fma(b, uc, cj);
                 bn = fma(b, b, bn);
+                if (PREC == MFMA_BF16) {
+                    const __bf16 h = to_bf16(uc);
+                    vh[e] = h;
+                    vl[e] = to_bf16(uc - from_bf16(h));
+                } else {
+                    vf[e] = (float)uc;
+                }
+            }
+        }
+        if (g < gfull) {
+            if (PREC == MFMA_BF16) {
+                h8[g] = vh;
+                l8[g] = vl;
+            } else {
+                f4[g] = vf;
+            }
+        }
+    }
+    cj += __shfl_xor(cj, 1);
+    bn += __shfl_xor(bn, 1);
+    cj += __shfl_xor(cj, 2);
+    bn += __shfl_xor(bn, 2);
+    // the pieces from coordinate d on, now that c_j is known
+    for (int64_t g = gfull + ((t - gfull) & 3); g < pieces; g += 4) {
+        v8bf vh{}, vl{};
+        v4f vf{};
+#pragma unroll
+        for (int e = 0; e < kE; ++e) {
+            const int64_t c = g * kE + e;
+            if (c < d) {
+                const double uc = u[c * ldm];
                 if (PREC == MFMA_BF16) {
                     const __bf16 h = to_bf16(uc);
                     vh[e] = h;
@@ -191,6 +232,7 @@ __global__ __launch_bounds__(64) void k_prep_dirs(const double *__restrict__ UT,
             f4[g] = vf;
         }
     }
+    if (t != 0) return;
     // margin part that depends on the direction only: kappa |c_j| plus the
     // binary64 recipe's own error through |z - xbar|; the data part
     // kappa' |a_i| is added per element
@@ -966,8 +1008,8 @@ hipError_t launch_mfma_dirs(int prec, bool fold, const double *UT, int64_t d, in
     const int64_t kp = mfma_kpad(prec, d);
     mfma_margins(prec, d, kp, &kappa, &canon);
     dim3 grid((unsigned)((npad + 63) / 64));
-#define RRS_DIRS(P, F)                                                                        \
-    hipLaunchKernelGGL((k_prep_dirs<P, F>), grid, dim3(64), 0, st, UT, d, m, ldm, ncols, npad, \
+#define RRS_DIRS(P, F)                                                                         \
+    hipLaunchKernelGGL((k_prep_dirs<P, F>), grid, dim3(256), 0, st, UT, d, m, ldm, ncols, npad, \
                        kp, Zb, xbar, kappa, canon, B0, B1, cmarg, amax, cq, eq, pp ? 1 : 0)
     if (prec == MFMA_BF16) {
         if (fold)
