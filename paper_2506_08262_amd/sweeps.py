@@ -46,7 +46,12 @@ LAWS = {"gaussian": toeplitz_gaussian, "exponential": rotated_exponential}
 
 
 def _depth(X, Z, K, r, alpha, seed, area_cap=False, precision="f32"):
+    """Projection depth; refinements of 65536 or more directions (beyond the
+    matrix-core forms' column index) run in binary64, which gives the same
+    depths as the binary32 form with its binary64 recheck."""
     from . import rrs
+    if precision != "f64" and -(-int(K) // int(r)) >= 65536:
+        precision = "f64"
     return rrs.depth("projection", X, Z, int(K), int(r), float(alpha), int(seed),
                      precision=precision, area_cap=area_cap)["depth"].cpu().numpy()
 
