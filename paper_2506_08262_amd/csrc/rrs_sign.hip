@@ -667,7 +667,9 @@ __global__ __launch_bounds__(256) void k_block_recheck(
 }
 
 // Per query: Delta_q = max_j |u_j - p_q| and |z_q - xbar| (binary32, rounded
-// up), and the cull thresholds lam_q, mu_q.  One workgroup per query.
+// up), and the cull thresholds lam_q, mu_q.  One workgroup per query; the
+// loads of eight coordinates go out before their fma steps, and wave 0 sums
+// |z_q - xbar|^2 over its lanes while the others finish their directions.
 __global__ __launch_bounds__(256) void k_cull_bounds(const double *__restrict__ UT, int64_t d,
                                                      int64_t m, int64_t ldm,
                                                      const double *__restrict__ pole,
@@ -681,16 +683,36 @@ __global__ __launch_bounds__(256) void k_cull_bounds(const double *__restrict__ 
     const int64_t q = blockIdx.x;
     const int tid = threadIdx.x;
     __shared__ double red[256];
+    __shared__ double bn_sh;
     const double *u = UT + q * d * ldm;
     const double *p = pole + q * d;
     double mx = 0.0;
     for (int64_t j = tid; j < m; j += 256) {
         double s = 0.0;
-        for (int64_t c = 0; c < d; ++c) {
+        int64_t c = 0;
+        for (; c + 8 <= d; c += 8) {
+            double e[8];
+#pragma unroll
+            for (int k = 0; k < 8; ++k) e[k] = u[(c + k) * ldm + j] - p[c + k];
+#pragma unroll
+            for (int k = 0; k < 8; ++k) s = fma(e[k], e[k], s);
+        }
+        for (; c < d; ++c) {
             const double e = u[c * ldm + j] - p[c];
             s = fma(e, e, s);
         }
         mx = fmax(mx, s);
+    }
+    if (tid < 64) {
+        // |z_q - xbar|^2 in lane-strided partial sums (the order only moves
+        // the sum by rounding, far inside the slack applied below)
+        double bn = 0.0;
+        for (int64_t c = tid; c < d; c += 64) {
+            const double b = Zb[q * d + c] - xbar[c];
+            bn = fma(b, b, bn);
+        }
+        for (int o = 32; o > 0; o >>= 1) bn += __shfl_xor(bn, o);
+        if (tid == 0) bn_sh = bn;
     }
     red[tid] = mx;
     __syncthreads();
@@ -703,12 +725,7 @@ __global__ __launch_bounds__(256) void k_cull_bounds(const double *__restrict__ 
         // squared norms; the factors below absorb that and the roundings to
         // binary32
         const double delta = sqrt(red[0]) * (1.0 + 1e-9);
-        double bn = 0.0;
-        for (int64_t c = 0; c < d; ++c) {
-            const double b = Zb[q * d + c] - xbar[c];
-            bn = fma(b, b, bn);
-        }
-        const double bnorm = sqrt(bn) * (1.0 + 1e-9);
+        const double bnorm = sqrt(bn_sh) * (1.0 + 1e-9);
         // |t^ - (x - z).p| <= kappa_a |a_i| + pmarg_q (the sign GEMM's
         // margin for the pole column), |x_i - z| <= |a_i| + |z - xbar|, and
         // the binary64 recipe of a projection is within gamma |x_i - z| of
