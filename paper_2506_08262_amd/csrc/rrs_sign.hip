@@ -649,9 +649,21 @@ __global__ __launch_bounds__(256) void k_block_recheck(
             const int64_t row = r0 + (k >> 4) * 32 + ((k >> 2) & 3) * 8 + (k & 3);
             const int64_t i = lists ? (int64_t)lists[qi * n + row] : row;
             const double *x = X + i * d;
+            // the recipe's fma chain in coordinate order, with the loads of
+            // eight coordinates issued ahead of their steps
             double t = 0.0;
-#pragma unroll 4
-            for (int64_t c = 0; c < d; ++c) t = fma(x[c] - z[c], u[c], t);
+            int64_t c = 0;
+            for (; c + 8 <= d; c += 8) {
+                double xv[8], uv[8];
+#pragma unroll
+                for (int k = 0; k < 8; ++k) {
+                    xv[k] = x[c + k];
+                    uv[k] = u[c + k];
+                }
+#pragma unroll
+                for (int k = 0; k < 8; ++k) t = fma(xv[k] - z[c + k], uv[k], t);
+            }
+            for (; c < d; ++c) t = fma(x[c] - z[c], u[c], t);
             le += t <= 0.0 ? 1u : 0u;
             ge += t >= 0.0 ? 1u : 0u;
         }
