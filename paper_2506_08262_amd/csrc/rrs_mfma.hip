@@ -74,22 +74,47 @@ __global__ __launch_bounds__(256) void k_prep_data(const double *__restrict__ X,
     const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
     double ss = 0.0;
     if (i < n) {
-        // column d (and d + 1 for BF16) multiplies the folded centring term
+        // column d (and d + 1 for BF16) multiplies the folded centring term.
+        // The row goes out in 16-byte pieces (8 bf16 or 4 binary32 elements;
+        // kp is a multiple of 16 or 8), the loads of a piece's coordinates
+        // issued together
         const int64_t nfold = PREC == MFMA_BF16 ? 2 : 1;
-        for (int64_t c = 0; c < kp; ++c) {
-            double a = 0.0;
-            if (c < d) {
-                a = X[i * d + c] - xbar[c];
-                ss = fma(a, a, ss);
-            } else if (c < d + nfold) {
-                a = 1.0;
+        constexpr int kE = PREC == MFMA_BF16 ? 8 : 4;
+        typedef __attribute__((ext_vector_type(8))) __bf16 v8bf;
+        typedef __attribute__((ext_vector_type(4))) float v4f;
+        const double *x = X + i * d;
+        for (int64_t g = 0; g < kp / kE; ++g) {
+            double xv[kE];
+#pragma unroll
+            for (int e = 0; e < kE; ++e) {
+                const int64_t c = g * kE + e;
+                xv[e] = c < d ? x[c] - xbar[c] : 0.0;
+            }
+            v8bf vh{}, vl{};
+            v4f vf{};
+#pragma unroll
+            for (int e = 0; e < kE; ++e) {
+                const int64_t c = g * kE + e;
+                double a = 0.0;
+                if (c < d) {
+                    a = xv[e];
+                    ss = fma(a, a, ss);
+                } else if (c < d + nfold) {
+                    a = 1.0;
+                }
+                if (PREC == MFMA_BF16) {
+                    const __bf16 h = to_bf16(a);
+                    vh[e] = h;
+                    vl[e] = c < d ? to_bf16(a - from_bf16(h)) : (__bf16)0.0f;
+                } else {
+                    vf[e] = (float)a;
+                }
             }
             if (PREC == MFMA_BF16) {
-                const __bf16 h = to_bf16(a);
-                ((__bf16 *)A0)[i * kp + c] = h;
-                ((__bf16 *)A1)[i * kp + c] = c < d ? to_bf16(a - from_bf16(h)) : (__bf16)0.0f;
+                ((v8bf *)A0)[i * (kp / kE) + g] = vh;
+                ((v8bf *)A1)[i * (kp / kE) + g] = vl;
             } else {
-                ((float *)A0)[i * kp + c] = (float)a;
+                ((v4f *)A0)[i * (kp / kE) + g] = vf;
             }
         }
         // upper bound of the norm, rounded up to binary32
