@@ -430,8 +430,6 @@ rrs_status enqueue_job(const JobSpec &s, const DataDev &D, const Plan &p, const 
                     RRS_HIP_TRY(launch_mfma_dirs(p.prec, true, pole, d, 1, 1, nb, npad_pole, Zb,
                                                  D.xbar, P0, P1, pmarg, D.amax, nullptr, nullptr,
                                                  st));
-                    RRS_HIP_TRY(launch_fill_u32(lcount, nb, 0u, st));
-                    RRS_HIP_TRY(launch_fill_u32(base, nb * 2, 0u, st));
                     CullArgs ca{pole,  D.xbar, P0,     P1,   pmarg,
                                 npad_pole, lam, mu,   lists, lcount,
                                 base,  offs,  items, qctl + 4, list_pct,

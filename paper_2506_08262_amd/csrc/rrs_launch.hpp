@@ -172,8 +172,8 @@ struct CullArgs {
     int64_t npad_pole;
     float *lam, *mu;           // [qb] cull thresholds
     uint32_t *lists;           // [qb][n] out: undecided points
-    uint32_t *lcount;          // [qb] out (zeroed by the caller)
-    uint32_t *base;            // [qb][2] out: decided points below / above (zeroed)
+    uint32_t *lcount;          // [qb] out (launch_cull zeroes it first)
+    uint32_t *base;            // [qb][2] out: decided points below / above (zeroed first)
     uint32_t *offs;            // [qb + 1] out: item offsets of the list-mode GEMM
     uint32_t *items;           // [sign_max_items][4] out: the items themselves
     uint32_t *mode;            // out: 1 = the sign GEMM runs over the lists, 0 = dense

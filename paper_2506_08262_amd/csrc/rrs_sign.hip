@@ -679,9 +679,11 @@ __global__ __launch_bounds__(256) void k_block_recheck(
 }
 
 // Per query: Delta_q = max_j |u_j - p_q| and |z_q - xbar| (binary32, rounded
-// up), and the cull thresholds lam_q, mu_q.  One workgroup per query; the
-// loads of eight coordinates go out before their fma steps, and wave 0 sums
-// |z_q - xbar|^2 over its lanes while the others finish their directions.
+// up), and the cull thresholds lam_q, mu_q; also zeroes the query's list
+// count and decided counts, which the cull GEMM then accumulates.  One
+// workgroup per query; the loads of eight coordinates go out before their fma
+// steps, and wave 0 sums |z_q - xbar|^2 over its lanes while the others
+// finish their directions.
 __global__ __launch_bounds__(256) void k_cull_bounds(const double *__restrict__ UT, int64_t d,
                                                      int64_t m, int64_t ldm,
                                                      const double *__restrict__ pole,
@@ -690,10 +692,17 @@ __global__ __launch_bounds__(256) void k_cull_bounds(const double *__restrict__ 
                                                      const float *__restrict__ pmarg,
                                                      float kappa_a, double gamma,
                                                      float *__restrict__ lam,
-                                                     float *__restrict__ mu)
+                                                     float *__restrict__ mu,
+                                                     uint32_t *__restrict__ lcount,
+                                                     uint32_t *__restrict__ base)
 {
     const int64_t q = blockIdx.x;
     const int tid = threadIdx.x;
+    if (tid == 0) {
+        lcount[q] = 0u;
+        base[2 * q] = 0u;
+        base[2 * q + 1] = 0u;
+    }
     __shared__ double red[256];
     __shared__ double bn_sh;
     const double *u = UT + q * d * ldm;
@@ -973,7 +982,8 @@ hipError_t launch_cull(const SignArgs &a, const CullArgs &c, hipStream_t st)
     // thresholds per query
     const double gamma = 4.0 * (double)(a.d + 2) * ldexp(1.0, -53);
     hipLaunchKernelGGL(k_cull_bounds, dim3((unsigned)a.qb), dim3(256), 0, st, a.UT, a.d, a.m,
-                       a.ldm, c.pole, a.Z, c.xbar, c.pmarg, kappa_a, gamma, c.lam, c.mu);
+                       a.ldm, c.pole, a.Z, c.xbar, c.pmarg, kappa_a, gamma, c.lam, c.mu,
+                       c.lcount, c.base);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     SignParams p{};
