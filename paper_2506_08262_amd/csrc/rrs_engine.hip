@@ -392,7 +392,14 @@ rrs_status enqueue_job(const JobSpec &s, const DataDev &D, const Plan &p, const 
     uint32_t *items = cv.take<uint32_t>(sz[25] / 4);
     double *UR = p.sign ? cv.take<double>(sz[26] / 8) : nullptr;
     const int64_t npad_pole = p.cull ? mfma_col_pad(qb) : 0;
-    const double cull_angle = env_double("RRS_CULL_ANGLE", 1.5707963267948966);
+    // Culling at refinement l decides the points whose angle to the pole's
+    // hyperplane exceeds the cap's half-angle eps_l; for data spread over d
+    // dimensions that angle's sine is about |N(0,1)| / sqrt(d), so caps with
+    // sin(eps_l) > 3 / sqrt(d) decide almost nothing and the cull pass is
+    // skipped there (the dense GEMM follows either way).  RRS_CULL_ANGLE
+    // overrides the largest half-angle.
+    const double cull_angle = env_double(
+        "RRS_CULL_ANGLE", asin(fmin(1.0, 3.0 / sqrt((double)(d > 0 ? d : 1)))));
     // lists when their matrix-core work is below this percent of the dense
     // GEMM's (RRS_LIST_PCT: 0 always dense, 1000 always lists)
     const int list_pct = (int)env_double("RRS_LIST_PCT", 80.0);

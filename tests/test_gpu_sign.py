@@ -57,7 +57,11 @@ def _check(w, q0=0, **kw):
     (2500, 110, 300, 3, "mixture"),     # seven (the 1e5 x 100 workload's padding)
     (1300, 126, 200, 4, "gaussian"),    # eight
 ])
-def test_sign_gemm_shapes(n, d, K, r, law):
+def test_sign_gemm_shapes(n, d, K, r, law, monkeypatch):
+    # culling at every refinement l >= 2 (by default wide caps in many
+    # dimensions skip it), so that the cull GEMM and the list-mode sign GEMM
+    # run at every K padding
+    monkeypatch.setenv("RRS_CULL_ANGLE", "1.5707963267948966")
     w = workloads.small("halfspace", n, d, 9, K, r, 0.6, law=law, seed_cfg=5 * n + d)
     _check(w)
 
