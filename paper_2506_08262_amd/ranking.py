@@ -61,11 +61,14 @@ def rank_correlations(a: np.ndarray, b: np.ndarray) -> dict:
 
 def study(d: int, n: int = 100_000, queries: int = 5000, K: int = 100_000, n_refine: int = 40,
           cap_shrink: float = 0.9, law: str = "gaussian", nu: float = 0.0, seed: int = 0,
-          precision: str = "f32", device: str = "cuda:0", first_cap: bool = False) -> dict:
+          precision: str = "f32", device: str = "cuda:0", first_cap: bool = False,
+          chunk: int = 500) -> dict:
     """One column of the study: depths D_P and D_AP and D_M(L) (all on the
     GPU) of `queries` points drawn from the n-point data set, correlated with
     the true density and with each other.  first_cap: refinement 1 draws in
-    the half-angle pi/2 cap around e1 (Alg. S4) instead of on the sphere."""
+    the half-angle pi/2 cap around e1 (Alg. S4) instead of on the sphere.
+    The queries go to the library in calls of `chunk` rows, each with its
+    stream offset, so the depths are those of a single call."""
     import torch
 
     from . import rrs
@@ -83,11 +86,18 @@ def study(d: int, n: int = 100_000, queries: int = 5000, K: int = 100_000, n_ref
     for notion in ("projection", "apd"):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        res = rrs.depth(notion, Xt, Zt, K, n_refine, cap_shrink, seed, precision=precision,
-                        first_cap=first_cap)
+        parts = []
+        for q0 in range(0, queries, chunk):
+            res = rrs.depth(notion, Xt, Zt[q0:q0 + chunk], K, n_refine, cap_shrink, seed,
+                            precision=precision, first_cap=first_cap, query_offset=q0)
+            parts.append(res["depth"])
+            if queries > chunk:
+                torch.cuda.synchronize()
+                print(f"[ranking] {notion}: {min(q0 + chunk, queries)}/{queries} queries",
+                      file=sys.stderr, flush=True)
         torch.cuda.synchronize()
         sec = time.perf_counter() - t0
-        depths[notion] = res["depth"].cpu().numpy()
+        depths[notion] = torch.cat(parts).cpu().numpy()
         print(f"[ranking] {law} nu={nu} d={d} {notion}: {sec:.1f} s", file=sys.stderr, flush=True)
         m = -(-K // n_refine)
         out[f"{notion}_seconds"] = sec
@@ -117,12 +127,14 @@ def main(argv=None) -> None:
                          "matrix-core forms' selects to per-point error bounds)")
     ap.add_argument("--first-cap", action="store_true",
                     help="refinement 1 in the pi/2 cap around e1 instead of on the sphere")
+    ap.add_argument("--chunk", type=int, default=500,
+                    help="queries per library call (stream offsets keep the depths of one call)")
     args = ap.parse_args(argv)
     runs = [("gaussian", 0.0, d) for d in args.dims] + [("t", nu, 50) for nu in args.nus]
     for law, nu, d in runs:
         r = study(d, args.n, args.queries, args.K, args.n_refine, args.cap_shrink, law, nu,
                   precision=args.precision if law == "gaussian" else args.t_precision,
-                  first_cap=args.first_cap)
+                  first_cap=args.first_cap, chunk=args.chunk)
         print(json.dumps(r), flush=True)
         print(f"[ranking] {law} nu={nu} d={d} done", file=sys.stderr, flush=True)
 

@@ -30,3 +30,14 @@ def test_ranking_study_depths_match_the_oracle():
                         0.9, 0, precision="f32")["depth"].cpu().numpy()
         ref = oracle.rrs_depth(notion, X, Z, 400, 8, 0.9, 0)["depth"]
         assert np.array_equal(got, ref), notion
+
+
+def test_chunked_study_equals_one_call():
+    """The study hands its queries to the library in chunks with their stream
+    offsets: the depths and correlations equal those of a single call."""
+    one = ranking.study(5, n=3000, queries=60, K=600, n_refine=6, cap_shrink=0.9,
+                        precision="f32", chunk=60)
+    parts = ranking.study(5, n=3000, queries=60, K=600, n_refine=6, cap_shrink=0.9,
+                          precision="f32", chunk=17)
+    for key in ("pdf_x_DP", "pdf_x_DAP", "DP_x_DAP"):
+        assert one[key] == parts[key], key
